@@ -1,0 +1,218 @@
+"""FP64 CPU oracle for the combined ray query (ctypes wrapper over oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the package smoke check
+and the CPU-baseline leg of the benchmark, never by the GPU library.  It shares
+no code with the GPU path.
+
+Every function takes the exact FP32 inputs the GPU sees and computes in FP64:
+  closest_hit   O-1  closest triangle on [a,b] (Section 2, Eq. (1) on a sub-interval)
+  sdf_nodes     O-5  exact signed distance to the mesh at grid nodes
+  df_hit        O-3  first root of the trilinear interpolant on [a,b]
+  sphere_trace  cross-check of df_hit by plain sphere tracing
+  query         O-4  combined / triangles-only / DF-only query (Section 2, Eq. (2))
+  margin        per-ray distance from a decision boundary, for parity filtering
+  df_grad       O-6  d t_hit / d grid sample by implicit differentiation
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MODE_COMBINED, MODE_BVH, MODE_DF = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (-O2, OpenMP, FP64, no hand SIMD)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, f32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_double
+        L.oracle_closest_hit.argtypes = [P, P, i64, P, i64, P, P, P, P, P, P]
+        L.oracle_sdf_nodes.argtypes = [P, P, i64, P, P, P, i32, P, i32, P, i64, i32, P]
+        L.oracle_df_hit.argtypes = [P, i32, P, P, i64, P, P, P]
+        L.oracle_df_value.argtypes = [P, i32, P, f64, f64, f64]
+        L.oracle_df_value.restype = f64
+        L.oracle_lipschitz.argtypes = [P, i32, f64]
+        L.oracle_lipschitz.restype = f64
+        L.oracle_sphere_trace.argtypes = [P, i32, P, f64, P, i64, P, P, f64, i64, P, P]
+        L.oracle_query.argtypes = [P, P, i64, P, i32, P, P, i64, P, f32, f32, i32, P, P, P, P]
+        L.oracle_margin.argtypes = [P, P, i64, P, i32, P, P, i64, P, f32, f32, i32, P, P]
+        L.oracle_df_grad.argtypes = [P, i32, P, P, i64, P, P, P, P, P]
+        L.oracle_sdf_points.argtypes = [P, P, i64, P, P, P, i32, P, i64, P]
+        L.oracle_df_values.argtypes = [P, i32, P, P, i64, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _rays(rays_soa):
+    r = _f32(rays_soa)
+    assert r.ndim == 2 and r.shape[0] == 6
+    return r, r.shape[1]
+
+
+def closest_hit(verts, tris, rays_soa, a, b):
+    v, t = _f32(verts), _i32(tris)
+    r, n = _rays(rays_soa)
+    a = _f64(np.broadcast_to(a, (n,)))
+    b = _f64(np.broadcast_to(b, (n,)))
+    to, uo, vo = np.empty(n), np.empty(n), np.empty(n)
+    po = np.empty(n, dtype=np.int32)
+    lib().oracle_closest_hit(_p(v), _p(t), t.shape[0], _p(r), n, _p(a), _p(b), _p(to), _p(po), _p(uo), _p(vo))
+    return to, po, uo, vo
+
+
+def sdf_nodes(scene, grid4, n, nodes=None, prune=True):
+    """Exact signed distance (FP64) at node indices i + n(j + n k); all nodes
+    when `nodes` is None.  Returns FP64 values; the stored grid is their FP32
+    rounding."""
+    v, t = _f32(scene.verts), _i32(scene.tris)
+    g4 = _f32(grid4)
+    if nodes is None:
+        nodes = np.arange(n ** 3, dtype=np.int64)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.empty(len(nodes))
+    lib().oracle_sdf_nodes(_p(v), _p(t), t.shape[0], _p(_i32(scene.group_start)), _p(_i32(scene.group_count)),
+                           _p(_i32(scene.group_kind)), len(scene.group_kind), _p(g4), n, _p(nodes), len(nodes),
+                           1 if prune else 0, _p(out))
+    return out
+
+
+def sdf_grid(scene, grid4, n):
+    """Full exact grid, FP32, shape (n,n,n) indexed [k,j,i] (x fastest)."""
+    return sdf_nodes(scene, grid4, n).astype(np.float32).reshape(n, n, n)
+
+
+def _grid(grid):
+    """Grid samples as FP64 (FP32 grids are promoted exactly)."""
+    return _f64(grid)
+
+
+def sdf_points(scene, pts):
+    """Exact signed distance (FP64) at arbitrary points (n,3)."""
+    v, t = _f32(scene.verts), _i32(scene.tris)
+    p = _f64(pts).reshape(-1, 3)
+    out = np.empty(len(p))
+    lib().oracle_sdf_points(_p(v), _p(t), t.shape[0], _p(_i32(scene.group_start)), _p(_i32(scene.group_count)),
+                            _p(_i32(scene.group_kind)), len(scene.group_kind), _p(p), len(p), _p(out))
+    return out
+
+
+def df_hit(grid, grid4, rays_soa, a, b):
+    g = _grid(grid)
+    N = g.shape[-1]
+    r, n = _rays(rays_soa)
+    a = _f64(np.broadcast_to(a, (n,)))
+    b = _f64(np.broadcast_to(b, (n,)))
+    out = np.empty(n)
+    lib().oracle_df_hit(_p(g), N, _p(_f32(grid4)), _p(r), n, _p(a), _p(b), _p(out))
+    return out
+
+
+def df_value(grid, grid4, p):
+    g = _grid(grid)
+    return lib().oracle_df_value(_p(g), g.shape[-1], _p(_f32(grid4)), float(p[0]), float(p[1]), float(p[2]))
+
+
+def df_values(grid, grid4, pts):
+    """Interpolant at points (n,3)."""
+    g = _grid(grid)
+    p = _f64(pts).reshape(-1, 3)
+    out = np.empty(len(p))
+    lib().oracle_df_values(_p(g), g.shape[-1], _p(_f32(grid4)), _p(p), len(p), _p(out))
+    return out
+
+
+def lipschitz(grid, h):
+    g = _grid(grid)
+    return lib().oracle_lipschitz(_p(g), g.shape[-1], float(h))
+
+
+def sphere_trace(grid, grid4, L, rays_soa, a, b, eps, max_steps=1_000_000):
+    g = _grid(grid)
+    r, n = _rays(rays_soa)
+    a = _f64(np.broadcast_to(a, (n,)))
+    b = _f64(np.broadcast_to(b, (n,)))
+    out = np.empty(n)
+    st = np.empty(n, dtype=np.int32)
+    lib().oracle_sphere_trace(_p(g), g.shape[-1], _p(_f32(grid4)), float(L), _p(r), n, _p(a), _p(b),
+                              float(eps), int(max_steps), _p(out), _p(st))
+    return out, st
+
+
+def query(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=MODE_COMBINED, tmin=None):
+    """O-4.  Returns (t, prim, u, v); prim -1 miss, -2 distance-field hit."""
+    v, t = _f32(verts), _i32(tris)
+    g = None if grid is None else _grid(grid)
+    N = 0 if g is None else g.shape[-1]
+    r, n = _rays(rays_soa)
+    tm = None if tmin is None else _f32(tmin)
+    to, uo, vo = np.empty(n), np.empty(n), np.empty(n)
+    po = np.empty(n, dtype=np.int32)
+    lib().oracle_query(_p(v), _p(t), t.shape[0], _p(g), N, None if grid4 is None else _p(_f32(grid4)),
+                       _p(r), n, _p(tm), np.float32(tmax), np.float32(tau), mode,
+                       _p(to), _p(po), _p(uo), _p(vo))
+    return to, po, uo, vo
+
+
+def margin(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=MODE_COMBINED, tmin=None):
+    """Per-ray (margin, conditioning) of query(): see oracle.c."""
+    v, t = _f32(verts), _i32(tris)
+    g = None if grid is None else _grid(grid)
+    N = 0 if g is None else g.shape[-1]
+    r, n = _rays(rays_soa)
+    tm = None if tmin is None else _f32(tmin)
+    mo, co = np.empty(n), np.empty(n)
+    lib().oracle_margin(_p(v), _p(t), t.shape[0], _p(g), N, None if grid4 is None else _p(_f32(grid4)),
+                        _p(r), n, _p(tm), np.float32(tmax), np.float32(tau), mode, _p(mo), _p(co))
+    return mo, co
+
+
+def df_grad(grid, grid4, rays_soa, t_hit, a=0.0, b=np.inf):
+    """O-6: per ray, 8 node indices and d t_hit / d sample (node -1: none) for
+    DF hits on the segments [a,b]."""
+    g = _grid(grid)
+    r, n = _rays(rays_soa)
+    th = _f64(t_hit)
+    a = _f64(np.broadcast_to(a, (n,)))
+    b = _f64(np.broadcast_to(b, (n,)))
+    nodes = np.empty((n, 8), dtype=np.int64)
+    dt = np.empty((n, 8))
+    lib().oracle_df_grad(_p(g), g.shape[-1], _p(_f32(grid4)), _p(r), n, _p(a), _p(b), _p(th), _p(nodes), _p(dt))
+    return nodes, dt

@@ -1,0 +1,494 @@
+"""Pins of the FP64 oracle against facts fixed outside it: hand-computed cases,
+closed forms (slab test, plane, sphere, box SDF), invariants of the
+interpolant, and brute force on tiny inputs.  The paper prints no worked
+numeric example, so every pin is mathematical.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2305_07253_amd import workloads as W
+
+
+def soa(o, d):
+    o = np.asarray(o, dtype=np.float32).reshape(-1, 3)
+    d = np.asarray(d, dtype=np.float32).reshape(-1, 3)
+    return np.ascontiguousarray(np.concatenate([o.T, d.T]))
+
+
+def mesh_scene(verts, tris, kinds=None, starts=None, counts=None):
+    """A Scene wrapper around an explicit mesh (one group unless given)."""
+    verts = np.asarray(verts, dtype=np.float32)
+    tris = np.asarray(tris, dtype=np.int32)
+    if kinds is None:
+        kinds, starts, counts = [W.KIND_BOX], [0], [len(tris)]
+    G = len(kinds)
+    return W.Scene(verts, tris, np.array(starts, np.int32), np.array(counts, np.int32), np.array(kinds, np.int32),
+                   np.zeros((G, 3)), np.tile(np.eye(3), (G, 1, 1)), np.zeros((G, 3)), 0)
+
+
+def rot_box(c, ext, R, n=1):
+    v, f = W._box_mesh(n)
+    return (c + (v * ext) @ R.T).astype(np.float32), f.astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# O-1: closest triangle hit
+# ---------------------------------------------------------------------------
+
+def test_o1_hand_case(orc):
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+    t, p, u, vv = orc.closest_hit(v, [[0, 1, 2]], soa([0.25, 0.25, 1], [0, 0, -1]), 0.0, 10.0)
+    assert p[0] == 0 and t[0] == 1.0 and u[0] == 0.25 and vv[0] == 0.25
+    # back face (no culling)
+    t, p, u, vv = orc.closest_hit(v, [[0, 1, 2]], soa([0.25, 0.25, -2], [0, 0, 1]), 0.0, 10.0)
+    assert p[0] == 0 and t[0] == 2.0
+    # parallel ray misses
+    t, p, _, _ = orc.closest_hit(v, [[0, 1, 2]], soa([0.25, 0.25, 0], [1, 0, 0]), 0.0, 10.0)
+    assert p[0] == -1 and np.isinf(t[0])
+    # the interval is closed: t = a and t = b are hits, just outside is not
+    for a, b, hit in ((1.0, 2.0, True), (0.0, 1.0, True), (0.0, 0.999, False), (1.001, 2.0, False)):
+        t, p, _, _ = orc.closest_hit(v, [[0, 1, 2]], soa([0.25, 0.25, 1], [0, 0, -1]), a, b)
+        assert (p[0] == 0) == hit
+
+
+def test_o1_tie_goes_to_smallest_id(orc):
+    # two triangles sharing the edge (0,0,0)-(1,1,0); the ray crosses the edge
+    v = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]], np.float32)
+    for tris in ([[0, 1, 2], [0, 2, 3]], [[0, 2, 3], [0, 1, 2]]):
+        t, p, _, _ = orc.closest_hit(v, tris, soa([0.5, 0.5, 1], [0, 0, -1]), 0.0, 10.0)
+        assert p[0] == 0 and t[0] == 1.0
+    # a duplicated triangle: identical t, smaller index wins
+    t, p, _, _ = orc.closest_hit(v, [[0, 2, 3], [0, 1, 2], [0, 1, 2]], soa([0.7, 0.2, 1], [0, 0, -1]), 0, 10)
+    assert p[0] == 1
+
+
+def slab(o, d, lo, hi):
+    """Analytic ray/box entry: (t_enter, axis) or None."""
+    t0, t1, ax = -np.inf, np.inf, -1
+    for a in range(3):
+        if d[a] == 0:
+            if not lo[a] <= o[a] <= hi[a]:
+                return None
+            continue
+        ta, tb = (lo[a] - o[a]) / d[a], (hi[a] - o[a]) / d[a]
+        if ta > tb:
+            ta, tb = tb, ta
+        if ta > t0:
+            t0, ax = ta, a
+        t1 = min(t1, tb)
+    return (t0, ax) if t0 <= t1 and t1 >= 0 else None
+
+
+def test_o1_box_against_slab(orc):
+    rng = np.random.default_rng(5)
+    R = W._random_rotation(rng)
+    c, ext = np.array([0.5, 0.4, 0.6]), np.array([0.2, 0.1, 0.15])
+    v, f = rot_box(c, ext, R, n=3)
+    n = 2000
+    o = c + rng.normal(size=(n, 3)) * 0.6
+    d = W._normalize32(c + rng.normal(size=(n, 3)) * 0.1 - o)
+    o = o.astype(np.float32)
+    t, p, u, vv = orc.closest_hit(v, f, soa(o, d), 0.0, 10.0)
+    vd = v.astype(np.float64)
+    checked = 0
+    for i in range(n):
+        # box frame: exact slab test on the rotated box (the mesh is that box up to FP32 vertex rounding)
+        ol = (o[i].astype(np.float64) - c) @ R
+        dl = d[i].astype(np.float64) @ R
+        s = slab(ol, dl, -ext, ext)
+        if s is None or s[0] < 0:
+            continue
+        checked += 1
+        assert p[i] >= 0
+        assert abs(t[i] - s[0]) < 1e-6
+        # barycentrics reproduce the hit point on the reported triangle
+        tri = vd[f[p[i]]]
+        hit = (1 - u[i] - vv[i]) * tri[0] + u[i] * tri[1] + vv[i] * tri[2]
+        assert np.allclose(hit, o[i] + t[i] * d[i].astype(np.float64), atol=1e-12)
+        # and the triangle lies on the face the slab test entered through
+        nrm = np.cross(tri[1] - tri[0], tri[2] - tri[0]) @ R
+        assert np.argmax(np.abs(nrm)) == s[1]
+    assert checked > 500
+
+
+def test_o1_icosphere_between_sphere_and_inball(orc):
+    rng = np.random.default_rng(6)
+    V, F = W._icosphere_mesh(2)
+    r, c = 0.3, np.array([0.5, 0.5, 0.5])
+    v = (c + r * V).astype(np.float32)
+    vd = v.astype(np.float64)
+    tri = vd[F]
+    nrm = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    r_in = np.min(np.einsum("ij,ij->i", tri[:, 0] - c, nrm))
+    n = 1000
+    o = c + W._normalize32(rng.normal(size=(n, 3))).astype(np.float64) * 0.9
+    d = W._normalize32(c + rng.normal(size=(n, 3)) * 0.1 - o)
+    o = o.astype(np.float32)
+    t, p, _, _ = orc.closest_hit(v, F, soa(o, d), 0.0, 10.0)
+    ok = 0
+    for i in range(n):
+        oo, dd = o[i].astype(np.float64), d[i].astype(np.float64)
+        def ball(rad):
+            b = np.dot(oo - c, dd)
+            disc = b * b - (np.dot(oo - c, oo - c) - rad * rad)
+            return None if disc < 0 else -b - math.sqrt(disc)
+        ts, ti = ball(r), ball(r_in)
+        if ti is None:
+            continue
+        ok += 1
+        assert p[i] >= 0 and ts - 1e-12 <= t[i] <= ti + 1e-12
+    assert ok > 500
+
+
+# ---------------------------------------------------------------------------
+# O-5: exact signed distance
+# ---------------------------------------------------------------------------
+
+def room_and_box(R, c, ext, n=6):
+    rv, rf = W._box_mesh(1)
+    rv = 0.5 + 0.5 * rv
+    rf = rf[:, ::-1]
+    bv, bf = rot_box(c, ext, R, n)
+    verts = np.concatenate([rv, bv]).astype(np.float32)
+    tris = np.concatenate([rf, bf + len(rv)]).astype(np.int32)
+    return mesh_scene(verts, tris, [W.KIND_ROOM, W.KIND_BOX], [0, len(rf)], [len(rf), len(bf)])
+
+
+def box_sdf(p, c, R, ext):
+    q = np.abs((p - c) @ R) - ext
+    return np.linalg.norm(np.maximum(q, 0), axis=1) + np.minimum(q.max(axis=1), 0)
+
+
+def test_o5_box_against_analytic(orc):
+    rng = np.random.default_rng(7)
+    R = W._random_rotation(rng)
+    c, ext = np.array([0.5, 0.5, 0.5]), np.array([0.12, 0.08, 0.1])
+    sc = room_and_box(R, c, ext)
+    p = c + rng.normal(size=(4000, 3)) * 0.12
+    f = orc.sdf_points(sc, p)
+    fb = box_sdf(p, c, R, ext)
+    walls = np.minimum(p, 1 - p).min(axis=1)
+    near_box = np.abs(fb) < walls - 1e-3
+    assert near_box.sum() > 3000
+    # vertices are FP32-rounded, so the mesh is the box to ~1e-8
+    assert np.abs(f[near_box] - fb[near_box]).max() < 1e-7
+
+
+def test_o5_empty_room_and_exterior(orc):
+    rv, rf = W._box_mesh(1)
+    sc = mesh_scene(0.5 + 0.5 * rv, rf[:, ::-1], [W.KIND_ROOM], [0], [12])
+    g4 = W.room_grid(16)
+    N = 16
+    f = orc.sdf_nodes(sc, g4, N)
+    i = np.arange(N ** 3)
+    ijk = np.stack([i % N, (i // N) % N, i // N ** 2], axis=1)
+    p = g4[:3].astype(np.float64) + ijk * np.float64(g4[3])
+    inside = np.all((p > 0) & (p < 1), axis=1)
+    expect_in = np.minimum(p, 1 - p).min(axis=1)
+    # exterior: negative Euclidean distance to the cube
+    q = np.abs(p - 0.5) - 0.5
+    expect_out = -np.linalg.norm(np.maximum(q, 0), axis=1) + np.minimum(q.max(axis=1), 0) * 0
+    assert np.abs(f[inside] - expect_in[inside]).max() < 1e-15
+    on_or_out = ~inside
+    assert np.all(f[on_or_out] <= 0)
+    strict_out = np.any((p < 0) | (p > 1), axis=1)
+    assert np.abs(f[strict_out] - expect_out[strict_out]).max() < 1e-15
+
+
+def test_o5_pruning_is_exact(orc, tiny):
+    g4, N = tiny["grid4"], 32
+    nodes = np.arange(0, N ** 3, 5)
+    a = orc.sdf_nodes(tiny["scene"], g4, N, nodes=nodes, prune=True)
+    b = orc.sdf_nodes(tiny["scene"], g4, N, nodes=nodes, prune=False)
+    assert np.array_equal(a, b)
+
+
+def test_o5_sign_matches_object_records(orc, tiny):
+    sc = tiny["scene"]
+    rng = np.random.default_rng(8)
+    p = rng.uniform(-0.1, 1.1, size=(20000, 3))
+    f = orc.sdf_points(sc, p)
+    solid = np.any((p <= 0) | (p >= 1), axis=1)
+    for g in range(1, len(sc.group_kind)):
+        loc = (p - sc.centers[g]) @ sc.rots[g]
+        if sc.group_kind[g] == W.KIND_BOX:
+            solid |= np.all(np.abs(loc) <= sc.extents[g], axis=1)
+    # icospheres: compare only away from their circumsphere/inball shell
+    clear = np.abs(f) > 1e-6
+    is_box_only = np.ones(len(p), bool)
+    for g in range(1, len(sc.group_kind)):
+        if sc.group_kind[g] == W.KIND_ICO:
+            rr = np.linalg.norm(p - sc.centers[g], axis=1)
+            s = sc.extents[g][0]
+            inball = rr < 0.79 * s  # 80-face icosphere inradius is ~0.795 r
+            solid |= inball
+            is_box_only &= ~((rr >= 0.79 * s) & (rr <= s))
+    sel = clear & is_box_only
+    assert sel.sum() > 15000
+    assert np.array_equal(f[sel] < 0, solid[sel])
+
+
+# ---------------------------------------------------------------------------
+# O-2 / O-3: interpolant and its first root
+# ---------------------------------------------------------------------------
+
+def linear_grid(N, g4, a, b):
+    i = np.arange(N)
+    x = g4[0] + i * np.float64(g4[3])
+    X, Y, Z = np.meshgrid(x, x, x, indexing="xy")
+    # grid is indexed [k][j][i] with x fastest
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    return a[0] * X + a[1] * Y + a[2] * Z + b
+
+
+def test_o2_trilinear_exact_for_linear(orc):
+    N, g4 = 12, np.array([-0.1, -0.1, -0.1, 0.1], np.float32)
+    a, b = np.array([0.3, -0.7, 0.2]), 0.05
+    grid = linear_grid(N, g4, a, b)
+    rng = np.random.default_rng(9)
+    p = rng.uniform(-0.1, 1.0, size=(5000, 3))
+    assert np.abs(orc.df_values(grid, g4, p) - (p @ a + b)).max() < 1e-14
+
+
+def test_o3_plane_hit_is_analytic(orc):
+    N, g4 = 24, np.array([-0.1, -0.1, -0.1, 0.05], np.float32)
+    nrm = np.array([0.2, -0.5, 0.84])
+    nrm /= np.linalg.norm(nrm)
+    off = 0.4
+    grid = linear_grid(N, g4, nrm, -off)  # f = n.p - off: half-space SDF
+    rng = np.random.default_rng(10)
+    o = rng.uniform(0.0, 1.0, size=(3000, 3)).astype(np.float32)
+    d = W._normalize32(rng.normal(size=(3000, 3)))
+    t = orc.df_hit(grid, g4, soa(o, d), 0.0, 5.0)
+    od, dd = o.astype(np.float64), d.astype(np.float64)
+    f0 = od @ nrm - off
+    tp = -f0 / (dd @ nrm)
+    # inside at the start: hit at t = 0
+    assert np.all(t[f0 <= 0] == 0.0)
+    # from outside: the plane hit if it is inside the grid box, else a miss
+    hi = g4[0] + (N - 1) * np.float64(g4[3])
+    hit = (f0 > 0) & (tp >= 0)
+    pe = od + tp[:, None] * dd
+    in_box = np.all((pe >= g4[0]) & (pe <= hi), axis=1) & (tp <= 5.0)
+    sel = hit & in_box
+    assert sel.sum() > 300
+    assert np.abs(t[sel] - tp[sel]).max() < 1e-12
+    assert np.all(np.isinf(t[(f0 > 0) & (tp < 0)]))
+
+
+def test_o3_sphere_within_interpolation_bound(orc):
+    N = 40
+    h = 1.0 / 32
+    g4 = np.array([-4 * h, -4 * h, -4 * h, h], np.float32)
+    c, r = np.array([0.5, 0.47, 0.52]), 0.3
+    x = g4[0] + np.arange(N) * np.float64(g4[3])
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    grid = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) - r
+    rng = np.random.default_rng(11)
+    n = 3000
+    o = (c + W._normalize32(rng.normal(size=(n, 3))) * 0.45).astype(np.float32)
+    d = W._normalize32(c + rng.normal(size=(n, 3)) * 0.12 - o)
+    t = orc.df_hit(grid, g4, soa(o, d), 0.0, 2.0)
+    od, dd = o.astype(np.float64), d.astype(np.float64)
+    b = np.einsum("ij,ij->i", od - c, dd)
+    disc = b * b - (np.einsum("ij,ij->i", od - c, od - c) - r * r)
+    ok = disc > 0
+    ts = -b - np.sqrt(np.where(ok, disc, 0))
+    cos = np.abs(np.einsum("ij,ij->i", (od + ts[:, None] * dd - c) / r, dd))
+    sel = ok & (cos > 0.3)
+    assert sel.sum() > 1000
+    # trilinear error of a C2 function: (h^2/8) * sum_i max|f_ii|, |f_ii| <= 1/rho, rho >= r - sqrt(3) h
+    bound = (3 * h * h / (8 * (r - math.sqrt(3) * h))) / cos[sel]
+    assert np.all(np.abs(t[sel] - ts[sel]) <= 1.2 * bound)
+
+
+def test_o3_dense_sampling_agrees(orc, tiny):
+    """Brute force: the first of dense samples (spacing 1e-3 h) with g <= 0."""
+    grid, g4 = tiny["grid"], tiny["grid4"]
+    h = np.float64(g4[3])
+    r = tiny["free"].subset(slice(0, 48))
+    t = orc.df_hit(grid, g4, r.soa(), 0.0, 2.0)
+    m, _ = orc.margin(None, np.zeros((0, 3)), grid, g4, r.soa(), 2.0, 0.0, mode=orc.MODE_DF)
+    step = 1e-3 * h
+    for i in range(r.n):
+        if not m[i] > 1e-5:
+            continue
+        end = min(t[i] + 2 * step, 2.0) if np.isfinite(t[i]) else 2.0
+        ts = np.arange(0.0, end, step)
+        p = r.o[i].astype(np.float64) + ts[:, None] * r.d[i].astype(np.float64)
+        g = orc.df_values(grid, g4, p)
+        below = np.nonzero(g <= 0)[0]
+        if np.isfinite(t[i]):
+            assert len(below) > 0
+            td = ts[below[0]]
+            assert t[i] <= td + 1e-15 and td - t[i] <= step + 1e-15
+        else:
+            assert len(below) == 0
+
+
+def test_o3_sphere_tracer_agrees(orc, tiny):
+    grid, g4 = tiny["grid"], tiny["grid4"]
+    h = np.float64(g4[3])
+    L = orc.lipschitz(grid, h)
+    assert 1.0 <= L <= math.sqrt(3) + 1e-6
+    for rays in (tiny["free"], tiny["surf"]):
+        t = orc.df_hit(grid, g4, rays.soa(), 0.0, 2.0)
+        ts, st = orc.sphere_trace(grid, g4, L, rays.soa(), 0.0, 2.0, 1e-12 * h)
+        m, c = orc.margin(None, np.zeros((0, 3)), grid, g4, rays.soa(), 2.0, 0.0, mode=orc.MODE_DF)
+        sel = (m > 1e-5) & (st == 0)
+        assert sel.mean() > 0.95
+        assert np.array_equal(np.isfinite(t[sel]), np.isfinite(ts[sel]))
+        both = sel & np.isfinite(t) & (c > 1e-2)
+        assert np.all(np.abs(ts[both] - t[both]) <= 1e-12 * np.maximum(t[both], 0.05))
+
+
+def test_o3_never_passes_surface_beyond_grid_error(orc, tiny):
+    """For the exact, 1-Lipschitz SDF f sampled on the grid, |f~ - f| <= E =
+    (sqrt(3)/2) h (+ FP32 storage error q): before the DF hit the exact field
+    stays above -(E+q), and at the hit it is at most E+q."""
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    h = np.float64(g4[3])
+    E, q = math.sqrt(3) / 2 * h, 1e-7
+    r = tiny["free"].subset(slice(0, 256))
+    t = orc.df_hit(grid, g4, r.soa(), 0.0, 2.0)
+    assert np.isfinite(t).all()  # the room is closed
+    pts, hits = [], []
+    for i in range(r.n):
+        ts = np.arange(0.0, t[i], h / 4)
+        pts.append(r.o[i] + ts[:, None] * r.d[i].astype(np.float64))
+        hits.append(r.o[i] + t[i] * r.d[i].astype(np.float64))
+    f_before = orc.sdf_points(sc, np.concatenate(pts))
+    f_hit = orc.sdf_points(sc, np.array(hits))
+    assert f_before.min() > -(E + q)
+    assert f_hit.max() <= E + q and f_hit.min() >= -(E + q)
+
+
+# ---------------------------------------------------------------------------
+# O-4: combined query
+# ---------------------------------------------------------------------------
+
+TAUS = (0.0, 0.5, 1.0, 2.0, 4.0, np.inf)
+
+
+def test_o4_limits(orc, tiny):
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    for rays in (tiny["free"], tiny["surf"]):
+        s = rays.soa()
+        bvh = orc.query(sc.verts, sc.tris, grid, g4, s, 2.0, np.inf, mode=orc.MODE_BVH)
+        df = orc.query(sc.verts, sc.tris, grid, g4, s, 2.0, 0.0, mode=orc.MODE_DF)
+        c_inf = orc.query(sc.verts, sc.tris, grid, g4, s, 2.0, np.inf)
+        c_0 = orc.query(sc.verts, sc.tris, grid, g4, s, 2.0, 0.0)
+        for a, b in zip(bvh, c_inf):
+            assert np.array_equal(a, b)
+        for a, b in zip(df, c_0):
+            assert np.array_equal(a, b)
+
+
+def test_o4_decomposition_identity(orc, tiny):
+    """Eq. (2), first hit in order: the triangle answer on [tmin,t1] if there is
+    one, else the distance-field answer on [t1,tmax]."""
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    h = np.float32(g4[3])
+    for rays in (tiny["free"], tiny["surf"]):
+        s = rays.soa()
+        for tau in TAUS[1:-1]:
+            t1 = np.float64(min(np.float32(np.float32(tau) * h), np.float32(2.0)))  # tmin = 0: fma == product
+            c = orc.query(sc.verts, sc.tris, grid, g4, s, 2.0, tau)
+            seg = orc.closest_hit(sc.verts, sc.tris, s, 0.0, t1)
+            rest = orc.df_hit(grid, g4, s, t1, 2.0)
+            hit1 = seg[1] >= 0
+            assert np.array_equal(c[1][hit1], seg[1][hit1]) and np.array_equal(c[0][hit1], seg[0][hit1])
+            assert np.array_equal(c[0][~hit1], rest[~hit1])
+            assert np.all(c[1][~hit1] == np.where(np.isfinite(rest[~hit1]), -2, -1))
+
+
+def test_o4_segment_one_monotone(orc, tiny):
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    s = tiny["surf"].soa()
+    prev = None
+    for tau in TAUS[1:]:
+        caught = orc.query(sc.verts, sc.tris, grid, g4, s, 2.0, tau)[1] >= 0
+        if prev is not None:
+            assert np.all(caught[prev])
+        prev = caught
+
+
+def test_o4_empty_interval_and_tmin(orc, tiny):
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    r = tiny["free"].subset(slice(0, 64))
+    tmin = np.full(64, 3.0, np.float32)  # tmin > tmax: a miss, not an error
+    t, p, _, _ = orc.query(sc.verts, sc.tris, grid, g4, r.soa(), 2.0, 1.0, tmin=tmin)
+    assert np.all(p == -1) and np.all(np.isinf(t))
+    # tmin shifts the interval: the answer never lies before tmin
+    tmin = np.full(64, 0.05, np.float32)
+    for mode in (0, 1, 2):
+        t, p, _, _ = orc.query(sc.verts, sc.tris, grid, g4, r.soa(), 2.0, 1.0, mode=mode, tmin=tmin)
+        assert np.all(t[p != -1] >= 0.05)
+
+
+# ---------------------------------------------------------------------------
+# O-6: gradient of the DF hit
+# ---------------------------------------------------------------------------
+
+def test_o6_planar_by_hand(orc):
+    """f = z - 0.45: a ray straight down from z = 0.9 hits at t = 0.45 with
+    g' = -1, so dt/dtheta_j = w_j (the trilinear weight of corner j)."""
+    N, h = 12, 0.1
+    g4 = np.array([-0.1, -0.1, -0.1, h], np.float32)
+    grid = linear_grid(N, g4, np.array([0.0, 0.0, 1.0]), -0.45)
+    o = np.array([[0.33, 0.47, 0.9]], np.float32)
+    d = np.array([[0, 0, -1]], np.float32)
+    t = orc.df_hit(grid, g4, soa(o, d), 0.0, 2.0)
+    od = o[0].astype(np.float64)
+    assert abs(t[0] - (od[2] - 0.45)) < 1e-12
+    nodes, dt = orc.df_grad(grid, g4, soa(o, d), t, 0.0, 2.0)
+    hh, lo = np.float64(g4[3]), np.float64(g4[0])
+    fx = (od[0] - lo) / hh - 4  # cell 4 in x: x = -0.1 + 4*0.1 = 0.3
+    fy = (od[1] - lo) / hh - 5
+    fz = (0.45 - lo) / hh - 5
+    wsum = 0.0
+    for j in range(8):
+        bx, by, bz = j & 1, (j >> 1) & 1, (j >> 2) & 1
+        w = (fx if bx else 1 - fx) * (fy if by else 1 - fy) * (fz if bz else 1 - fz)
+        assert abs(dt[0, j] - w) < 1e-6
+        wsum += dt[0, j]
+    assert abs(wsum - 1.0) < 1e-9
+
+
+def test_o6_finite_differences(orc, tiny):
+    """Central differences of sum(t_hit) in FP64 on 64 voxels with non-zero
+    gradient, delta = 1e-6 h."""
+    grid = tiny["grid"].astype(np.float64)
+    g4 = tiny["grid4"]
+    h = np.float64(g4[3])
+    r = tiny["free"].subset(slice(0, 512))
+    s = r.soa()
+    t = orc.df_hit(grid, g4, s, 0.0, 2.0)
+    m, c = orc.margin(None, np.zeros((0, 3)), grid, g4, s, 2.0, 0.0, mode=orc.MODE_DF)
+    # the interpolant's gradient jumps across cell faces, so FD is only
+    # meaningful for hits clear of a face (room walls lie on a node plane)
+    p = r.o.astype(np.float64) + np.where(np.isfinite(t), t, 0)[:, None] * r.d.astype(np.float64)
+    x = (p - np.float64(g4[0])) / h
+    face = np.abs(x - np.round(x)).min(axis=1)
+    keep = np.isfinite(t) & (t > 0) & (m > 1e-4) & (c > 0.05) & (face > 1e-3)
+    r = r.subset(np.nonzero(keep)[0])
+    s = r.soa()
+    t = orc.df_hit(grid, g4, s, 0.0, 2.0)
+    nodes, dt = orc.df_grad(grid, g4, s, t, 0.0, 2.0)
+    grad = np.zeros(grid.size)
+    np.add.at(grad, nodes[nodes >= 0], dt[nodes >= 0])
+    cand = np.nonzero(grad)[0]
+    rng = np.random.default_rng(12)
+    pick = rng.choice(cand, size=64, replace=False)
+    delta = 1e-6 * h
+    flat = grid.reshape(-1)
+    for j in pick:
+        gp, gm = flat.copy(), flat.copy()
+        gp[j] += delta
+        gm[j] -= delta
+        tp = orc.df_hit(gp.reshape(grid.shape), g4, s, 0.0, 2.0)
+        tm = orc.df_hit(gm.reshape(grid.shape), g4, s, 0.0, 2.0)
+        fd = (tp.sum() - tm.sum()) / (2 * delta)
+        assert abs(fd - grad[j]) <= 1e-5 * max(1.0, abs(grad[j])), (j, fd, grad[j])
