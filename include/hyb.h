@@ -1,0 +1,166 @@
+/*
+ * hyb.h - combined BVH + distance-field ray queries on AMD Instinct MI355X.
+ *
+ * C ABI of the method of Bartels & Harada, "Combining GPU Tracing Methods
+ * within a Single Ray Query" (SIGGRAPH Asia 2022 Technical Communications).
+ *
+ * A ray query (o, d, tmin, tmax) (Section 2, Eq. 1) is split at
+ *     t1 = min(tmin + threshold * h, tmax)            (Section 3, occlusion queries:
+ *                                                      t1 from the voxel size h times a
+ *                                                      user multiplier)
+ * into two mutually exclusive sub-queries (Section 2, Eq. 2): [tmin, t1] is
+ * traced exactly against the triangles through a BVH, and only when that finds
+ * nothing (first-hit queries process sub-queries in order and stop at the first
+ * intersection, Section 2) is [t1, tmax] traced against a distance field.
+ * threshold = 0 gives pure distance-field tracing, threshold = +inf pure
+ * triangle tracing (the "pure" techniques of Section 3).
+ *
+ * Conventions shared by every entry point
+ *  - All pointers documented as "device" are HIP device pointers on the current
+ *    device; "host" pointers are ordinary CPU memory.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Trace calls
+ *    are asynchronous on `stream`; build calls return after their work on
+ *    `stream` has completed.
+ *  - The library owns handles until *_destroy.  Builders copy their inputs.  The
+ *    caller owns ray and hit buffers; trace calls allocate nothing.
+ *  - Errors come back as a status, never as a crash or an exception.  A status
+ *    other than HYB_OK leaves outputs unspecified.
+ *  - Handles are immutable after build: concurrent trace calls on different
+ *    streams are safe.
+ */
+#ifndef HYB_H
+#define HYB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HYB_OK = 0,
+    HYB_ERR_INVALID_ARG = 1, /* NULL pointer, bad size, NaN or negative tmax/threshold */
+    HYB_ERR_OOM = 2,         /* device allocation failed */
+    HYB_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed */
+    HYB_ERR_UNSUPPORTED = 4  /* valid input the library cannot handle (e.g. BVH deeper than 64) */
+} hyb_status;
+
+typedef struct hyb_bvh_s* hyb_bvh; /* triangle BVH; library-owned device memory */
+typedef struct hyb_sdf_s* hyb_sdf; /* distance-field grid; library-owned device memory */
+
+/* Storage of the distance-field samples. */
+typedef enum {
+    HYB_SDF_F32 = 0,     /* FP32 */
+    HYB_SDF_F16 = 1,     /* IEEE half */
+    HYB_SDF_I8_BRICK = 2 /* int8 with one FP32 scale per 8^3-cell brick */
+} hyb_sdf_format;
+
+/* Rays: device SoA arrays of n floats each.  d must be unit length (the
+ * distance-field steps assume it).  tmin may be NULL (tmin = 0 for every ray);
+ * a ray with tmin > tmax is reported as a miss. */
+typedef struct {
+    const float *ox, *oy, *oz;
+    const float *dx, *dy, *dz;
+    const float* tmin;
+} hyb_rays;
+
+/* Hits: caller-allocated device SoA arrays of n entries.
+ *   prim >= 0       triangle hit; prim is the triangle's index in the input mesh;
+ *                   the hit point is (1-u-v) v0 + u v1 + v v2.
+ *   prim == -2      distance-field hit (a distance field carries no surface
+ *                   identity, Section 2 "Surface information"); u = v = 0.
+ *   prim == -1      miss; t = +inf, u = v = 0.  */
+typedef struct {
+    float* t;
+    int32_t* prim;
+    float* u;
+    float* v;
+} hyb_hits;
+
+#define HYB_MISS (-1)
+#define HYB_DF_HIT (-2)
+
+/* hyb_build_sdf flag: space outside every closed surface is solid (a scene
+ * enclosed by an inward-facing room). */
+#define HYB_SDF_EXTERIOR_SOLID 1u
+
+/* Build a BVH over an indexed triangle mesh (the structure the paper's
+ * hardware ray tracing traverses, Section 3).
+ *   verts  host, n_verts x 3 floats (x,y,z)
+ *   tris   host, n_tris x 3 int32 vertex indices; 0 <= index < n_verts
+ * n_tris == 0 is allowed (every ray misses).  Degenerate triangles are kept and
+ * are never hit.  Errors: NULL pointers with nonzero counts, negative counts,
+ * out-of-range indices or non-finite vertices -> HYB_ERR_INVALID_ARG. */
+hyb_status hyb_build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                         void* stream, hyb_bvh* out);
+
+/* Number of BVH nodes, triangles and the tree depth. */
+hyb_status hyb_bvh_info(hyb_bvh bvh, int64_t* n_nodes, int64_t* n_tris, int32_t* depth);
+
+/* Build an n^3 node-centred signed distance grid from the BVH's mesh: each
+ * sample is the exact Euclidean distance to the nearest triangle (computed in
+ * FP64, rounded to FP32), negative inside solid space (winding number by signed
+ * crossing count).  This replaces the paper's voxelization + jump flooding +
+ * fast sweeping pipeline (Section 3, distance field generation) with exact
+ * values.
+ *   grid4  host, {lo_x, lo_y, lo_z, h}: node (i,j,k) sits at lo + (i,j,k) h.
+ *          NULL: the mesh bounding box padded by 2 voxels per side,
+ *          h = largest extent / (n - 5).
+ *   n      samples per axis, 8 <= n <= 1024.
+ *   flags  HYB_SDF_EXTERIOR_SOLID or 0.
+ *   fmt    storage format.
+ * Errors: HYB_ERR_INVALID_ARG for a NULL bvh/out, bad n, h <= 0 or non-finite
+ * grid4; HYB_ERR_OOM when the grid does not fit. */
+hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t flags, hyb_sdf_format fmt,
+                         void* stream, hyb_sdf* out);
+
+/* Wrap caller-provided samples as a distance field (copied).
+ *   values  device, n^3 floats, x fastest: values[i + n (j + n k)]
+ *   grid4   host, {lo_x, lo_y, lo_z, h}
+ * The Lipschitz bound used for safe steps is recomputed from the values. */
+hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4, hyb_sdf_format fmt,
+                             void* stream, hyb_sdf* out);
+
+/* Grid placement, resolution and the Lipschitz bound L of the trilinear
+ * interpolant of the stored samples (steps of g/L never pass a root). */
+hyb_status hyb_sdf_info(hyb_sdf sdf, float* grid4 /* host, 4 */, int32_t* n, float* lipschitz);
+
+/* Copy the samples as the trace kernels see them (dequantized for compact
+ * formats) into out (device, n^3 floats, x fastest). */
+hyb_status hyb_sdf_read(hyb_sdf sdf, float* out, void* stream);
+
+/* The combined first-hit query (Section 2, Eq. 2; Section 3): triangles on
+ * [tmin, t1], then the distance field on [t1, tmax] only for rays that found
+ * no triangle, with t1 = min(fl32(tmin + threshold * h), tmax).
+ *   tmax       0 <= tmax, may be +inf
+ *   threshold  0 <= threshold, in voxels of the grid, may be +inf
+ * n == 0 is a no-op.  Errors: HYB_ERR_INVALID_ARG for NULL handles/pointers,
+ * n < 0, NaN or negative tmax/threshold. */
+hyb_status hyb_trace(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, float threshold,
+                     hyb_hits* hits, void* stream);
+
+/* Pure triangle tracing on [tmin, tmax] (the paper's HWRT-only baseline). */
+hyb_status hyb_trace_bvh(hyb_bvh bvh, const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits, void* stream);
+
+/* Pure distance-field tracing on [tmin, tmax] (the paper's DF-only baseline). */
+hyb_status hyb_trace_df(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits, void* stream);
+
+/* Work counters of one query, for measurement: the same trace as hyb_trace
+ * (mode 0), hyb_trace_bvh (mode 1) or hyb_trace_df (mode 2), writing hits and,
+ * per ray, counts[3 i + 0] BVH nodes visited, counts[3 i + 1] triangles
+ * tested, counts[3 i + 2] distance-field sample fetches (8 corners each).
+ *   counts  device, 3 n int32.  bvh may be NULL for mode 2, sdf for mode 1. */
+hyb_status hyb_trace_counters(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax,
+                              float threshold, int32_t mode, hyb_hits* hits, int32_t* counts, void* stream);
+
+hyb_status hyb_bvh_destroy(hyb_bvh bvh);
+hyb_status hyb_sdf_destroy(hyb_sdf sdf);
+
+/* Static string naming a status. */
+const char* hyb_status_str(hyb_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYB_H */

@@ -61,8 +61,14 @@ def lib():
         L.oracle_df_grad.argtypes = [P, i32, P, P, i64, P, P, P, P, P]
         L.oracle_sdf_points.argtypes = [P, P, i64, P, P, P, i32, P, i64, P]
         L.oracle_df_values.argtypes = [P, i32, P, P, i64, P]
+        L.oracle_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(lib().oracle_threads())
 
 
 def _p(a):

@@ -23,9 +23,13 @@
  */
 #include <float.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Number of OpenMP threads the parallel loops use. */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 typedef struct { double x, y, z; } vec;
 

@@ -1,0 +1,286 @@
+"""Combined BVH + distance-field ray queries on AMD Instinct MI355X.
+
+Thin Python binding over the C ABI of libhyb.so (include/hyb.h): argument
+checks and marshalling only.  Every step of a query runs in the library's HIP
+kernels; PyTorch provides device memory and streams.  There is no CPU
+fallback: if libhyb.so is missing the calls raise.
+
+    import paper_2305_07253_amd as hyb
+    bvh = hyb.build_bvh(verts, tris)                 # host numpy arrays
+    sdf = hyb.build_sdf(bvh, 128, grid4)             # exact signed distance grid
+    t, prim, u, v = hyb.trace(bvh, sdf, rays, tmax=0.5, threshold=1.0)
+
+Rays are a (6, n) float32 CUDA tensor with rows ox, oy, oz, dx, dy, dz (unit
+directions); hits come back as float32 t, int32 prim (>= 0 triangle, -2
+distance-field hit, -1 miss), float32 u, v.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhyb.so")
+
+HYB_MISS = -1
+HYB_DF_HIT = -2
+EXTERIOR_SOLID = 1
+SDF_F32, SDF_F16, SDF_I8_BRICK = 0, 1, 2
+MODE_COMBINED, MODE_BVH, MODE_DF = 0, 1, 2
+
+_STATUS = {0: "HYB_OK", 1: "HYB_ERR_INVALID_ARG", 2: "HYB_ERR_OOM", 3: "HYB_ERR_HIP", 4: "HYB_ERR_UNSUPPORTED"}
+
+
+class HybError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        super().__init__("%s failed: %s" % (fn, _STATUS.get(status, status)))
+
+
+class _Rays(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("ox", "oy", "oz", "dx", "dy", "dz", "tmin")]
+
+
+class _Hits(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("t", "prim", "u", "v")]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libhyb.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhyb.so is not built (run `python -m paper_2305_07253_amd.build`); "
+                              "there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, f32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_uint32
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "hyb_build_bvh": [P, i64, P, i64, P, PP],
+            "hyb_bvh_info": [P, P, P, P],
+            "hyb_build_sdf": [P, i32, P, u32, i32, P, PP],
+            "hyb_sdf_from_grid": [P, i32, P, i32, P, PP],
+            "hyb_sdf_info": [P, P, P, P],
+            "hyb_sdf_read": [P, P, P],
+            "hyb_trace": [P, P, P, i64, f32, f32, P, P],
+            "hyb_trace_bvh": [P, P, i64, f32, P, P],
+            "hyb_trace_df": [P, P, i64, f32, P, P],
+            "hyb_trace_counters": [P, P, P, i64, f32, f32, i32, P, P, P],
+            "hyb_bvh_destroy": [P],
+            "hyb_sdf_destroy": [P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.hyb_status_str.argtypes = [ctypes.c_int]
+        L.hyb_status_str.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(fn, status):
+    if status != 0:
+        raise HybError(fn, status)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream, current=True):
+    """hipStream_t of a torch stream; None means torch's current stream for
+    trace calls and the default (NULL) stream for the synchronous builds."""
+    if stream is None:
+        if not current:
+            return ctypes.c_void_p(None)
+        stream = _torch().cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Bvh:
+    """Library-owned triangle BVH (device memory)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        n_nodes, n_tris, depth = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check("hyb_bvh_info", lib().hyb_bvh_info(handle, ctypes.byref(n_nodes), ctypes.byref(n_tris),
+                                                  ctypes.byref(depth)))
+        self.n_nodes, self.n_tris, self.depth = n_nodes.value, n_tris.value, depth.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hyb_bvh_destroy(self._h)
+            self._h = None
+
+
+class Sdf:
+    """Library-owned distance-field grid (device memory)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        g4 = (ctypes.c_float * 4)()
+        n, L = ctypes.c_int32(), ctypes.c_float()
+        _check("hyb_sdf_info", lib().hyb_sdf_info(handle, g4, ctypes.byref(n), ctypes.byref(L)))
+        self.grid4 = np.array(list(g4), dtype=np.float32)
+        self.n = n.value
+        self.lipschitz = L.value
+
+    @property
+    def h(self) -> float:
+        return float(self.grid4[3])
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hyb_sdf_destroy(self._h)
+            self._h = None
+
+
+def build_bvh(verts, tris, stream=None) -> Bvh:
+    """BVH over host arrays verts (V,3) float32 and tris (T,3) int32."""
+    v = np.ascontiguousarray(verts, dtype=np.float32).reshape(-1, 3)
+    t = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    out = ctypes.c_void_p()
+    _check("hyb_build_bvh", lib().hyb_build_bvh(v.ctypes.data_as(ctypes.c_void_p), v.shape[0],
+                                                t.ctypes.data_as(ctypes.c_void_p), t.shape[0],
+                                                _stream(stream, False), ctypes.byref(out)))
+    return Bvh(out)
+
+
+def build_sdf(bvh: Bvh, n: int, grid4=None, exterior_solid: bool = True, fmt: int = SDF_F32, stream=None) -> Sdf:
+    """Exact n^3 signed distance grid of the BVH's mesh; grid4 = [lo_x, lo_y,
+    lo_z, h] (float32) or None for the padded mesh bounds."""
+    g = None if grid4 is None else np.ascontiguousarray(grid4, dtype=np.float32)
+    out = ctypes.c_void_p()
+    _check("hyb_build_sdf", lib().hyb_build_sdf(bvh.handle, int(n), None if g is None else g.ctypes.data_as(
+        ctypes.c_void_p), EXTERIOR_SOLID if exterior_solid else 0, fmt, _stream(stream, False), ctypes.byref(out)))
+    return Sdf(out)
+
+
+def sdf_from_grid(values, grid4, fmt: int = SDF_F32, stream=None) -> Sdf:
+    """Wrap a CUDA float32 tensor of n^3 samples (x fastest) as a grid."""
+    torch = _torch()
+    if not (values.is_cuda and values.dtype == torch.float32 and values.is_contiguous()):
+        raise ValueError("values must be a contiguous float32 CUDA tensor")
+    n = round(values.numel() ** (1.0 / 3.0))
+    if n ** 3 != values.numel():
+        raise ValueError("values must hold n^3 samples")
+    g = np.ascontiguousarray(grid4, dtype=np.float32)
+    out = ctypes.c_void_p()
+    _check("hyb_sdf_from_grid", lib().hyb_sdf_from_grid(_ptr(values), n, g.ctypes.data_as(ctypes.c_void_p), fmt,
+                                                        _stream(stream), ctypes.byref(out)))
+    return Sdf(out)
+
+
+def sdf_read(sdf: Sdf, stream=None):
+    """The samples as the kernels see them: CUDA float32 tensor (n,n,n), [k,j,i]."""
+    torch = _torch()
+    out = torch.empty((sdf.n, sdf.n, sdf.n), dtype=torch.float32, device="cuda")
+    _check("hyb_sdf_read", lib().hyb_sdf_read(sdf.handle, _ptr(out), _stream(stream)))
+    return out
+
+
+def _rays_struct(rays, tmin):
+    torch = _torch()
+    if not (rays.is_cuda and rays.dtype == torch.float32 and rays.dim() == 2 and rays.shape[0] == 6
+            and rays.is_contiguous()):
+        raise ValueError("rays must be a contiguous (6, n) float32 CUDA tensor")
+    n = rays.shape[1]
+    base, step = rays.data_ptr(), 4 * n
+    r = _Rays(*[base + k * step for k in range(6)], None)
+    if tmin is not None:
+        if not (tmin.is_cuda and tmin.dtype == torch.float32 and tmin.numel() == n and tmin.is_contiguous()):
+            raise ValueError("tmin must be a contiguous float32 CUDA tensor of n entries")
+        r.tmin = tmin.data_ptr()
+    return r, n
+
+
+def alloc_hits(n: int, device="cuda"):
+    torch = _torch()
+    return (torch.empty(n, dtype=torch.float32, device=device), torch.empty(n, dtype=torch.int32, device=device),
+            torch.empty(n, dtype=torch.float32, device=device), torch.empty(n, dtype=torch.float32, device=device))
+
+
+def _hits_struct(out, n):
+    torch = _torch()
+    t, p, u, v = out
+    for x, dt in ((t, torch.float32), (p, torch.int32), (u, torch.float32), (v, torch.float32)):
+        if not (x.is_cuda and x.dtype == dt and x.numel() >= n and x.is_contiguous()):
+            raise ValueError("hit buffers must be contiguous CUDA tensors (f32, i32, f32, f32) of n entries")
+    return _Hits(t.data_ptr(), p.data_ptr(), u.data_ptr(), v.data_ptr())
+
+
+def _query_args(tmax, threshold):
+    if not (tmax >= 0.0) or math.isnan(tmax):
+        raise ValueError("tmax must be >= 0")
+    if threshold is not None and (not (threshold >= 0.0) or math.isnan(threshold)):
+        raise ValueError("threshold must be >= 0")
+
+
+def trace(bvh: Bvh, sdf: Sdf, rays, tmax: float, threshold: float, tmin=None, out=None, stream=None):
+    """Combined first-hit query: triangles on [tmin, t1], distance field on
+    [t1, tmax], t1 = min(tmin + threshold*h, tmax).  Returns (t, prim, u, v)."""
+    _query_args(tmax, threshold)
+    r, n = _rays_struct(rays, tmin)
+    out = alloc_hits(n) if out is None else out
+    h = _hits_struct(out, n)
+    _check("hyb_trace", lib().hyb_trace(bvh.handle, sdf.handle, ctypes.byref(r), n, tmax, threshold,
+                                        ctypes.byref(h), _stream(stream)))
+    return out
+
+
+def trace_bvh(bvh: Bvh, rays, tmax: float, tmin=None, out=None, stream=None):
+    """Pure triangle tracing on [tmin, tmax]."""
+    _query_args(tmax, None)
+    r, n = _rays_struct(rays, tmin)
+    out = alloc_hits(n) if out is None else out
+    h = _hits_struct(out, n)
+    _check("hyb_trace_bvh", lib().hyb_trace_bvh(bvh.handle, ctypes.byref(r), n, tmax, ctypes.byref(h),
+                                                _stream(stream)))
+    return out
+
+
+def trace_df(sdf: Sdf, rays, tmax: float, tmin=None, out=None, stream=None):
+    """Pure distance-field tracing on [tmin, tmax]."""
+    _query_args(tmax, None)
+    r, n = _rays_struct(rays, tmin)
+    out = alloc_hits(n) if out is None else out
+    h = _hits_struct(out, n)
+    _check("hyb_trace_df", lib().hyb_trace_df(sdf.handle, ctypes.byref(r), n, tmax, ctypes.byref(h),
+                                              _stream(stream)))
+    return out
+
+
+def trace_counters(bvh, sdf, rays, tmax: float, threshold: float, mode: int = MODE_COMBINED, tmin=None,
+                   stream=None):
+    """The same query with per-ray work counters: returns (t, prim, u, v) and
+    an int32 (n, 3) tensor of [BVH nodes, triangles tested, DF sample fetches]."""
+    torch = _torch()
+    _query_args(tmax, threshold)
+    r, n = _rays_struct(rays, tmin)
+    out = alloc_hits(n)
+    h = _hits_struct(out, n)
+    counts = torch.zeros((n, 3), dtype=torch.int32, device="cuda")
+    _check("hyb_trace_counters", lib().hyb_trace_counters(
+        None if bvh is None else bvh.handle, None if sdf is None else sdf.handle, ctypes.byref(r), n, tmax,
+        threshold, mode, ctypes.byref(h), _ptr(counts), _stream(stream)))
+    return out, counts

@@ -1,0 +1,329 @@
+// C API: argument validation, handle lifetime and launches on the caller's
+// stream.  Declared in include/hyb.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "bvh_build.hpp"
+#include "hyb.h"
+#include "hyb_device.hpp"
+#include "kernels.hpp"
+
+struct hyb_bvh_s {
+    int device = 0;
+    float4* nodes = nullptr;
+    float4* tris = nullptr;
+    int64_t n_nodes = 0, n_tris = 0;
+    int32_t depth = 0;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+};
+
+struct hyb_sdf_s {
+    int device = 0;
+    float* values = nullptr;  // n^3 FP32 samples, x fastest
+    int32_t n = 0;
+    float grid4[4] = {0, 0, 0, 0};
+    float lipschitz = 0.0f;
+    hyb_sdf_format fmt = HYB_SDF_F32;
+};
+
+namespace {
+
+hyb_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return HYB_OK;
+    if (e == hipErrorOutOfMemory) return HYB_ERR_OOM;
+    return HYB_ERR_HIP;
+}
+
+#define HYB_TRY(expr)                               \
+    do {                                            \
+        hyb_status s_ = from_hip(expr);             \
+        if (s_ != HYB_OK) return s_;                \
+    } while (0)
+
+bool same_device(int dev) {
+    int cur = -1;
+    return hipGetDevice(&cur) == hipSuccess && cur == dev;
+}
+
+bool valid_rays(const hyb_rays* r) {
+    return r && r->ox && r->oy && r->oz && r->dx && r->dy && r->dz;
+}
+
+bool valid_hits(const hyb_hits* h) { return h && h->t && h->prim && h->u && h->v; }
+
+// Lipschitz bound of the stored grid: per-block maxima on the device, final
+// maximum on the host (build time; synchronous).
+hyb_status compute_lipschitz(hyb_sdf_s* s, hipStream_t stream) {
+    const int32_t nb = hyb::lipschitz_blocks(s->n);
+    float* d_blocks = nullptr;
+    HYB_TRY(hipMalloc(&d_blocks, sizeof(float) * nb));
+    int32_t got = 0;
+    hipError_t e = hyb::launch_lipschitz(s->values, s->n, s->grid4[3], d_blocks, &got, stream);
+    std::vector<float> host(nb, 0.0f);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), d_blocks, sizeof(float) * nb, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(d_blocks);
+    HYB_TRY(e);
+    float L = 0.0f;
+    for (float v : host) L = std::max(L, v);
+    if (!std::isfinite(L)) return HYB_ERR_INVALID_ARG;
+    s->lipschitz = hyb::finish_lipschitz(L);
+    return HYB_OK;
+}
+
+bool valid_grid4(const float* g) {
+    return g && std::isfinite(g[0]) && std::isfinite(g[1]) && std::isfinite(g[2]) && std::isfinite(g[3]) &&
+           g[3] > 0.0f;
+}
+
+void fill_trace_args(hyb::TraceArgs& a, const hyb_rays* rays, hyb_hits* hits, int64_t n, float tmax, float tau) {
+    std::memset(&a, 0, sizeof(a));
+    a.ox = rays->ox; a.oy = rays->oy; a.oz = rays->oz;
+    a.dx = rays->dx; a.dy = rays->dy; a.dz = rays->dz;
+    a.tmin = rays->tmin;
+    a.t = hits->t; a.prim = hits->prim; a.u = hits->u; a.v = hits->v;
+    a.tmax = tmax;
+    a.tau = tau;
+    a.n = n;
+}
+
+void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s) {
+    if (b) {
+        a.nodes = b->nodes;
+        a.tris = b->tris;
+    }
+    if (s) {
+        a.sdf = s->values;
+        a.n_grid = s->n;
+        a.lo_x = s->grid4[0];
+        a.lo_y = s->grid4[1];
+        a.lo_z = s->grid4[2];
+        a.h = s->grid4[3];
+        a.inv_h = 1.0f / s->grid4[3];
+        a.inv_l = hyb::inv_step(s->lipschitz);
+    }
+}
+
+hyb_status check_query(const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits) {
+    if (n < 0 || std::isnan(tmax) || tmax < 0.0f) return HYB_ERR_INVALID_ARG;
+    if (n > 0 && (!valid_rays(rays) || !valid_hits(hits))) return HYB_ERR_INVALID_ARG;
+    return HYB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hyb_status_str(hyb_status s) {
+    switch (s) {
+        case HYB_OK: return "HYB_OK";
+        case HYB_ERR_INVALID_ARG: return "HYB_ERR_INVALID_ARG";
+        case HYB_ERR_OOM: return "HYB_ERR_OOM";
+        case HYB_ERR_HIP: return "HYB_ERR_HIP";
+        case HYB_ERR_UNSUPPORTED: return "HYB_ERR_UNSUPPORTED";
+    }
+    return "HYB_ERR_UNKNOWN";
+}
+
+hyb_status hyb_build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris, void* stream,
+                         hyb_bvh* out) {
+    if (!out) return HYB_ERR_INVALID_ARG;
+    *out = nullptr;
+    hyb::BvhHost host;
+    int rc = hyb::build_bvh_host(verts, n_verts, tris, n_tris, &host);
+    if (rc == 1) return HYB_ERR_INVALID_ARG;
+    if (rc != 0) return HYB_ERR_UNSUPPORTED;
+    hyb_bvh_s* b = new (std::nothrow) hyb_bvh_s;
+    if (!b) return HYB_ERR_OOM;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipGetDevice(&b->device);
+    b->n_nodes = static_cast<int64_t>(host.nodes.size() / 16);
+    b->n_tris = n_tris;
+    b->depth = host.depth;
+    for (int a = 0; a < 3; ++a) {
+        b->lo[a] = host.lo[a];
+        b->hi[a] = host.hi[a];
+    }
+    const size_t node_bytes = host.nodes.size() * sizeof(float);
+    const size_t tri_bytes = std::max<size_t>(host.tris.size(), 12) * sizeof(float);
+    if (e == hipSuccess) e = hipMalloc(&b->nodes, node_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b->tris, tri_bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->nodes, host.nodes.data(), node_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !host.tris.empty())
+        e = hipMemcpyAsync(b->tris, host.tris.data(), host.tris.size() * sizeof(float), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        hyb_bvh_destroy(b);
+        return from_hip(e);
+    }
+    *out = b;
+    return HYB_OK;
+}
+
+hyb_status hyb_bvh_info(hyb_bvh bvh, int64_t* n_nodes, int64_t* n_tris, int32_t* depth) {
+    if (!bvh) return HYB_ERR_INVALID_ARG;
+    if (n_nodes) *n_nodes = bvh->n_nodes;
+    if (n_tris) *n_tris = bvh->n_tris;
+    if (depth) *depth = bvh->depth;
+    return HYB_OK;
+}
+
+hyb_status hyb_bvh_destroy(hyb_bvh bvh) {
+    if (!bvh) return HYB_ERR_INVALID_ARG;
+    if (bvh->nodes) (void)hipFree(bvh->nodes);
+    if (bvh->tris) (void)hipFree(bvh->tris);
+    delete bvh;
+    return HYB_OK;
+}
+
+hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t flags, hyb_sdf_format fmt,
+                         void* stream, hyb_sdf* out) {
+    if (!out) return HYB_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!bvh || n < 8 || n > 1024 || (flags & ~HYB_SDF_EXTERIOR_SOLID)) return HYB_ERR_INVALID_ARG;
+    if (fmt != HYB_SDF_F32) return HYB_ERR_UNSUPPORTED;
+    if (!same_device(bvh->device)) return HYB_ERR_INVALID_ARG;
+    float g4[4];
+    if (grid4) {
+        if (!valid_grid4(grid4)) return HYB_ERR_INVALID_ARG;
+        std::memcpy(g4, grid4, sizeof(g4));
+    } else {
+        float ext = 0.0f;
+        for (int a = 0; a < 3; ++a) ext = std::max(ext, bvh->hi[a] - bvh->lo[a]);
+        g4[3] = ext > 0.0f ? ext / static_cast<float>(n - 5) : 1.0f;
+        for (int a = 0; a < 3; ++a) g4[a] = bvh->lo[a] - 2.0f * g4[3];
+    }
+    hyb_sdf_s* s = new (std::nothrow) hyb_sdf_s;
+    if (!s) return HYB_ERR_OOM;
+    s->device = bvh->device;
+    s->n = n;
+    s->fmt = fmt;
+    std::memcpy(s->grid4, g4, sizeof(g4));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t bytes = sizeof(float) * static_cast<size_t>(n) * n * n;
+    hipError_t e = hipMalloc(&s->values, bytes);
+    if (e == hipSuccess) {
+        hyb::SdfBuildArgs a;
+        a.nodes = bvh->nodes;
+        a.tris = bvh->tris;
+        a.n_grid = n;
+        a.lo_x = g4[0];
+        a.lo_y = g4[1];
+        a.lo_z = g4[2];
+        a.h = g4[3];
+        a.exterior_solid = (flags & HYB_SDF_EXTERIOR_SOLID) ? 1 : 0;
+        a.out = s->values;
+        e = hyb::launch_sdf_build(a, st);
+    }
+    hyb_status rc = from_hip(e);
+    if (rc == HYB_OK) rc = compute_lipschitz(s, st);
+    if (rc != HYB_OK) {
+        hyb_sdf_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return HYB_OK;
+}
+
+hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4, hyb_sdf_format fmt, void* stream,
+                             hyb_sdf* out) {
+    if (!out) return HYB_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!values || n < 2 || n > 1024 || !valid_grid4(grid4)) return HYB_ERR_INVALID_ARG;
+    if (fmt != HYB_SDF_F32) return HYB_ERR_UNSUPPORTED;
+    hyb_sdf_s* s = new (std::nothrow) hyb_sdf_s;
+    if (!s) return HYB_ERR_OOM;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipGetDevice(&s->device);
+    s->n = n;
+    s->fmt = fmt;
+    std::memcpy(s->grid4, grid4, sizeof(s->grid4));
+    const size_t bytes = sizeof(float) * static_cast<size_t>(n) * n * n;
+    if (e == hipSuccess) e = hipMalloc(&s->values, bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->values, values, bytes, hipMemcpyDeviceToDevice, st);
+    hyb_status rc = from_hip(e);
+    if (rc == HYB_OK) rc = compute_lipschitz(s, st);
+    if (rc != HYB_OK) {
+        hyb_sdf_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return HYB_OK;
+}
+
+hyb_status hyb_sdf_info(hyb_sdf sdf, float* grid4, int32_t* n, float* lipschitz) {
+    if (!sdf) return HYB_ERR_INVALID_ARG;
+    if (grid4) std::memcpy(grid4, sdf->grid4, sizeof(sdf->grid4));
+    if (n) *n = sdf->n;
+    if (lipschitz) *lipschitz = sdf->lipschitz;
+    return HYB_OK;
+}
+
+hyb_status hyb_sdf_read(hyb_sdf sdf, float* out, void* stream) {
+    if (!sdf || !out) return HYB_ERR_INVALID_ARG;
+    const size_t bytes = sizeof(float) * static_cast<size_t>(sdf->n) * sdf->n * sdf->n;
+    return from_hip(hipMemcpyAsync(out, sdf->values, bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+}
+
+hyb_status hyb_sdf_destroy(hyb_sdf sdf) {
+    if (!sdf) return HYB_ERR_INVALID_ARG;
+    if (sdf->values) (void)hipFree(sdf->values);
+    delete sdf;
+    return HYB_OK;
+}
+
+hyb_status hyb_trace(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, float threshold,
+                     hyb_hits* hits, void* stream) {
+    if (!bvh || !sdf || std::isnan(threshold) || threshold < 0.0f) return HYB_ERR_INVALID_ARG;
+    hyb_status rc = check_query(rays, n, tmax, hits);
+    if (rc != HYB_OK || n == 0) return rc;
+    if (!same_device(bvh->device) || !same_device(sdf->device)) return HYB_ERR_INVALID_ARG;
+    hyb::TraceArgs a;
+    fill_trace_args(a, rays, hits, n, tmax, threshold);
+    fill_scene(a, bvh, sdf);
+    return from_hip(hyb::launch_trace(hyb::kCombined, false, a, static_cast<hipStream_t>(stream)));
+}
+
+hyb_status hyb_trace_bvh(hyb_bvh bvh, const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits, void* stream) {
+    if (!bvh) return HYB_ERR_INVALID_ARG;
+    hyb_status rc = check_query(rays, n, tmax, hits);
+    if (rc != HYB_OK || n == 0) return rc;
+    if (!same_device(bvh->device)) return HYB_ERR_INVALID_ARG;
+    hyb::TraceArgs a;
+    fill_trace_args(a, rays, hits, n, tmax, __builtin_inff());
+    fill_scene(a, bvh, nullptr);
+    return from_hip(hyb::launch_trace(hyb::kBvhOnly, false, a, static_cast<hipStream_t>(stream)));
+}
+
+hyb_status hyb_trace_df(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits, void* stream) {
+    if (!sdf) return HYB_ERR_INVALID_ARG;
+    hyb_status rc = check_query(rays, n, tmax, hits);
+    if (rc != HYB_OK || n == 0) return rc;
+    if (!same_device(sdf->device)) return HYB_ERR_INVALID_ARG;
+    hyb::TraceArgs a;
+    fill_trace_args(a, rays, hits, n, tmax, 0.0f);
+    fill_scene(a, nullptr, sdf);
+    return from_hip(hyb::launch_trace(hyb::kDfOnly, false, a, static_cast<hipStream_t>(stream)));
+}
+
+hyb_status hyb_trace_counters(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, float threshold,
+                              int32_t mode, hyb_hits* hits, int32_t* counts, void* stream) {
+    if (mode < 0 || mode > 2 || std::isnan(threshold) || threshold < 0.0f) return HYB_ERR_INVALID_ARG;
+    if ((mode != 2 && !bvh) || (mode != 1 && !sdf)) return HYB_ERR_INVALID_ARG;
+    hyb_status rc = check_query(rays, n, tmax, hits);
+    if (rc != HYB_OK || n == 0) return rc;
+    if (!counts) return HYB_ERR_INVALID_ARG;
+    if ((bvh && !same_device(bvh->device)) || (sdf && !same_device(sdf->device))) return HYB_ERR_INVALID_ARG;
+    hyb::TraceArgs a;
+    fill_trace_args(a, rays, hits, n, tmax, mode == 1 ? __builtin_inff() : (mode == 2 ? 0.0f : threshold));
+    fill_scene(a, mode == 2 ? nullptr : bvh, mode == 1 ? nullptr : sdf);
+    a.counts = counts;
+    return from_hip(hyb::launch_trace(mode, true, a, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,278 @@
+// Binned-SAH BVH2 construction on the host (Wald, "On fast construction of
+// SAH-based bounding volume hierarchies", 2007: 32 bins per axis over the
+// centroid bounds), flattened into the 64-byte two-child node layout that the
+// device traversal reads with four 16-byte loads.
+#include "bvh_build.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+namespace hyb {
+namespace {
+
+constexpr int kBins = 32;
+constexpr float kTraversalCost = 1.0f;
+constexpr float kTriangleCost = 1.0f;
+
+struct Box {
+    float lo[3], hi[3];
+    void reset() {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::numeric_limits<float>::infinity();
+            hi[a] = -std::numeric_limits<float>::infinity();
+        }
+    }
+    void grow(const Box& b) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], b.lo[a]);
+            hi[a] = std::max(hi[a], b.hi[a]);
+        }
+    }
+    float area() const {
+        float e[3];
+        for (int a = 0; a < 3; ++a) e[a] = std::max(0.0f, hi[a] - lo[a]);
+        return 2.0f * (e[0] * e[1] + e[1] * e[2] + e[2] * e[0]);
+    }
+};
+
+struct Prim {
+    Box box;
+    float c[3];
+};
+
+struct TmpNode {
+    Box box;
+    int child[2] = {-1, -1};  // indices into the temporary node array
+    int first = 0, count = 0; // leaf range in the index array (count > 0 => leaf)
+};
+
+struct Builder {
+    const std::vector<Prim>& prims;
+    std::vector<int> idx;
+    std::vector<TmpNode> nodes;
+    int max_depth = 0;
+
+    explicit Builder(const std::vector<Prim>& p) : prims(p), idx(p.size()) {
+        for (size_t i = 0; i < p.size(); ++i) idx[i] = static_cast<int>(i);
+    }
+
+    int make_leaf(const Box& b, int first, int count) {
+        TmpNode n;
+        n.box = b;
+        n.first = first;
+        n.count = count;
+        nodes.push_back(n);
+        return static_cast<int>(nodes.size()) - 1;
+    }
+
+    // Builds the subtree over idx[first, first+count); returns its node index.
+    int build(int first, int count, int depth) {
+        max_depth = std::max(max_depth, depth);
+        Box bounds, cbounds;
+        bounds.reset();
+        cbounds.reset();
+        for (int i = first; i < first + count; ++i) {
+            const Prim& p = prims[idx[i]];
+            bounds.grow(p.box);
+            Box c;
+            for (int a = 0; a < 3; ++a) c.lo[a] = c.hi[a] = p.c[a];
+            cbounds.grow(c);
+        }
+        if (count == 1) return make_leaf(bounds, first, count);
+
+        // SAH sweep over the bins of every axis with a nonzero centroid extent.
+        float best_cost = std::numeric_limits<float>::infinity();
+        int best_axis = -1, best_split = -1;
+        const float parent_area = bounds.area();
+        for (int a = 0; a < 3; ++a) {
+            const float ext = cbounds.hi[a] - cbounds.lo[a];
+            if (!(ext > 0.0f)) continue;
+            const float scale = kBins / ext;
+            int cnt[kBins] = {};
+            Box bb[kBins];
+            for (int b = 0; b < kBins; ++b) bb[b].reset();
+            for (int i = first; i < first + count; ++i) {
+                const Prim& p = prims[idx[i]];
+                int b = std::min(kBins - 1, static_cast<int>((p.c[a] - cbounds.lo[a]) * scale));
+                cnt[b]++;
+                bb[b].grow(p.box);
+            }
+            float right_area[kBins];
+            int right_cnt[kBins];
+            Box acc;
+            acc.reset();
+            int n = 0;
+            for (int b = kBins - 1; b > 0; --b) {
+                acc.grow(bb[b]);
+                n += cnt[b];
+                right_area[b] = acc.area();
+                right_cnt[b] = n;
+            }
+            acc.reset();
+            n = 0;
+            for (int b = 0; b < kBins - 1; ++b) {
+                acc.grow(bb[b]);
+                n += cnt[b];
+                if (n == 0 || right_cnt[b + 1] == 0) continue;
+                float cost = kTraversalCost +
+                             kTriangleCost * (acc.area() * n + right_area[b + 1] * right_cnt[b + 1]) /
+                                 std::max(parent_area, 1e-30f);
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best_axis = a;
+                    best_split = b;
+                }
+            }
+        }
+
+        const float leaf_cost = kTriangleCost * count;
+        if (count <= kLeafMax && leaf_cost <= best_cost) return make_leaf(bounds, first, count);
+
+        int mid;
+        if (best_axis < 0) {
+            mid = first + count / 2;  // all centroids coincide: split by position in the list
+        } else {
+            const float ext = cbounds.hi[best_axis] - cbounds.lo[best_axis];
+            const float scale = kBins / ext;
+            const float lo = cbounds.lo[best_axis];
+            int* m = std::partition(idx.data() + first, idx.data() + first + count, [&](int i) {
+                int b = std::min(kBins - 1, static_cast<int>((prims[i].c[best_axis] - lo) * scale));
+                return b <= best_split;
+            });
+            mid = static_cast<int>(m - idx.data());
+            if (mid == first || mid == first + count) mid = first + count / 2;
+        }
+        TmpNode inner;
+        inner.box = bounds;
+        nodes.push_back(inner);
+        int self = static_cast<int>(nodes.size()) - 1;
+        int l = build(first, mid - first, depth + 1);
+        int r = build(mid, first + count - mid, depth + 1);
+        nodes[self].child[0] = l;
+        nodes[self].child[1] = r;
+        return self;
+    }
+};
+
+inline float bits_as_float(int32_t v) {
+    float f;
+    std::memcpy(&f, &v, 4);
+    return f;
+}
+
+}  // namespace
+
+int build_bvh_host(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris, BvhHost* out) {
+    if (n_verts < 0 || n_tris < 0 || (n_verts > 0 && !verts) || (n_tris > 0 && !tris) || !out) return 1;
+    if (n_tris > (int64_t(1) << 28)) return 4;
+    for (int64_t i = 0; i < 3 * n_verts; ++i)
+        if (!std::isfinite(verts[i])) return 1;
+    for (int64_t i = 0; i < 3 * n_tris; ++i)
+        if (tris[i] < 0 || tris[i] >= n_verts) return 1;
+
+    std::vector<Prim> prims(static_cast<size_t>(n_tris));
+    Box all;
+    all.reset();
+    for (int64_t t = 0; t < n_tris; ++t) {
+        Prim& p = prims[t];
+        p.box.reset();
+        for (int k = 0; k < 3; ++k) {
+            const float* v = verts + 3 * static_cast<int64_t>(tris[3 * t + k]);
+            Box pt;
+            for (int a = 0; a < 3; ++a) pt.lo[a] = pt.hi[a] = v[a];
+            p.box.grow(pt);
+        }
+        for (int a = 0; a < 3; ++a) p.c[a] = 0.5f * (p.box.lo[a] + p.box.hi[a]);
+        all.grow(p.box);
+    }
+    for (int a = 0; a < 3; ++a) {
+        out->lo[a] = n_tris ? all.lo[a] : 0.0f;
+        out->hi[a] = n_tris ? all.hi[a] : 0.0f;
+    }
+
+    Builder b(prims);
+    int root = -1;
+    if (n_tris > 0) root = b.build(0, static_cast<int>(n_tris), 1);
+    if (b.max_depth > kMaxDepth) return 4;
+
+    // Flatten depth-first: internal nodes get consecutive output indices, leaves
+    // become references into the leaf-ordered triangle array.
+    out->nodes.clear();
+    out->tris.assign(static_cast<size_t>(12 * n_tris), 0.0f);
+    int64_t tri_cursor = 0;
+    auto leaf_ref = [&](const TmpNode& n) -> int32_t {
+        int32_t first = static_cast<int32_t>(tri_cursor);
+        for (int i = 0; i < n.count; ++i) {
+            int t = b.idx[n.first + i];
+            float* dst = out->tris.data() + 12 * tri_cursor;
+            for (int k = 0; k < 3; ++k) {
+                const float* v = verts + 3 * static_cast<int64_t>(tris[3 * static_cast<int64_t>(t) + k]);
+                dst[4 * k + 0] = v[0];
+                dst[4 * k + 1] = v[1];
+                dst[4 * k + 2] = v[2];
+                dst[4 * k + 3] = k == 0 ? bits_as_float(t) : 0.0f;
+            }
+            ++tri_cursor;
+        }
+        return ~((first << 3) | n.count);
+    };
+    const float far = 1e30f;
+    Box empty_box;
+    for (int a = 0; a < 3; ++a) empty_box.lo[a] = empty_box.hi[a] = far;
+
+    // emit(node): writes the internal node and returns its output index
+    std::vector<std::pair<int, int>> todo;  // (tmp node, output slot)
+    auto alloc = [&]() {
+        out->nodes.resize(out->nodes.size() + 16, 0.0f);
+        return static_cast<int32_t>(out->nodes.size() / 16 - 1);
+    };
+    auto write_children = [&](int32_t slot, const Box& l, int32_t lref, const Box& r, int32_t rref) {
+        float* n = out->nodes.data() + 16 * static_cast<size_t>(slot);
+        n[0] = l.lo[0]; n[1] = l.hi[0]; n[2] = l.lo[1]; n[3] = l.hi[1];
+        n[4] = r.lo[0]; n[5] = r.hi[0]; n[6] = r.lo[1]; n[7] = r.hi[1];
+        n[8] = l.lo[2]; n[9] = l.hi[2]; n[10] = r.lo[2]; n[11] = r.hi[2];
+        n[12] = bits_as_float(lref); n[13] = bits_as_float(rref); n[14] = 0.0f; n[15] = 0.0f;
+    };
+
+    if (root < 0) {
+        int32_t s = alloc();
+        write_children(s, empty_box, kEmptyRef, empty_box, kEmptyRef);
+        out->depth = 1;
+        return 0;
+    }
+    if (b.nodes[root].count > 0) {
+        int32_t s = alloc();
+        int32_t lr = leaf_ref(b.nodes[root]);
+        write_children(s, b.nodes[root].box, lr, empty_box, kEmptyRef);
+        out->depth = 1;
+        return 0;
+    }
+    // iterative pre-order so the left child usually follows its parent in memory
+    std::vector<std::pair<int, int32_t>> stack;
+    stack.push_back({root, alloc()});
+    while (!stack.empty()) {
+        auto [tn, slot] = stack.back();
+        stack.pop_back();
+        const TmpNode& n = b.nodes[tn];
+        int32_t refs[2];
+        int32_t pending_slot[2] = {-1, -1};
+        for (int c = 0; c < 2; ++c) {
+            const TmpNode& ch = b.nodes[n.child[c]];
+            if (ch.count > 0) {
+                refs[c] = leaf_ref(ch);
+            } else {
+                pending_slot[c] = alloc();
+                refs[c] = pending_slot[c];
+            }
+        }
+        write_children(slot, b.nodes[n.child[0]].box, refs[0], b.nodes[n.child[1]].box, refs[1]);
+        for (int c = 1; c >= 0; --c)
+            if (pending_slot[c] >= 0) stack.push_back({n.child[c], pending_slot[c]});
+    }
+    out->depth = b.max_depth;
+    return 0;
+}
+
+}  // namespace hyb

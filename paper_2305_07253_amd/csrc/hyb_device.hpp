@@ -1,0 +1,452 @@
+// Device-side building blocks of the combined ray query (internal header).
+//
+// Everything here runs one ray per lane of a 64-wide CDNA wavefront:
+//   - robust ray/box slab test (Ize, "Robust BVH ray traversal", JCGT 2013)
+//   - watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013)
+//   - closest-hit BVH2 traversal with a per-lane stack in LDS (+ rare spill)
+//   - distance-field marching: conservative sphere-tracing steps g/L far from
+//     the surface, exact first root of the per-cell trilinear cubic near it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+// Per-ray functions are host+device so that a CPU build can run the exact
+// kernel logic (bounds-checked) against the oracle without a GPU.
+#define HYB_HD __host__ __device__ __forceinline__
+
+namespace hyb {
+
+constexpr int kBlock = 256;      // threads per block: 4 wavefronts
+constexpr int kLdsDepth = 16;    // stack entries per lane held in LDS
+constexpr int kStackDepth = 64;  // total stack entries per lane (LDS + spill)
+constexpr float kGamma3 = 3.0f * 5.9604645e-8f / (1.0f - 3.0f * 5.9604645e-8f);
+constexpr float kBoxPad = 1.0f + 2.0f * kGamma3;
+
+struct Counters {
+    int nodes = 0, tris = 0, df = 0;
+};
+
+HYB_HD float bits_f(int v) { return __builtin_bit_cast(float, v); }
+HYB_HD int bits_i(float v) { return __builtin_bit_cast(int, v); }
+
+HYB_HD float pick3(float a, float b, float c, int k) { return k == 0 ? a : (k == 1 ? b : c); }
+
+// ---------------------------------------------------------------------------
+// triangle test
+// ---------------------------------------------------------------------------
+
+// Per-ray shear of the watertight test: the ray becomes the +z axis.
+struct ShearRay {
+    int kx, ky, kz;
+    float sx, sy, sz;
+};
+
+HYB_HD ShearRay make_shear(float dx, float dy, float dz) {
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    ShearRay s;
+    s.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    s.kx = s.kz == 2 ? 0 : s.kz + 1;
+    s.ky = s.kx == 2 ? 0 : s.kx + 1;
+    const float dkz = pick3(dx, dy, dz, s.kz);
+    if (dkz < 0.0f) {
+        int t = s.kx;
+        s.kx = s.ky;
+        s.ky = t;
+    }
+    s.sx = pick3(dx, dy, dz, s.kx) / dkz;
+    s.sy = pick3(dx, dy, dz, s.ky) / dkz;
+    s.sz = 1.0f / dkz;
+    return s;
+}
+
+// Watertight test of one triangle against the ray on [t_lo, t_hi].  On a hit
+// returns true with t and barycentrics (u: weight of v1, v: weight of v2).
+// Contraction into FMA is disabled so that the edge functions of an edge shared
+// by two triangles are exact negations of each other.
+HYB_HD bool tri_hit(const ShearRay& s, float ox, float oy, float oz, float4 v0, float4 v1,
+                                        float4 v2, float t_lo, float t_hi, float& t, float& u, float& v) {
+#pragma clang fp contract(off)
+    const float Ax0 = v0.x - ox, Ay0 = v0.y - oy, Az0 = v0.z - oz;
+    const float Bx0 = v1.x - ox, By0 = v1.y - oy, Bz0 = v1.z - oz;
+    const float Cx0 = v2.x - ox, Cy0 = v2.y - oy, Cz0 = v2.z - oz;
+    const float Akz = pick3(Ax0, Ay0, Az0, s.kz), Bkz = pick3(Bx0, By0, Bz0, s.kz), Ckz = pick3(Cx0, Cy0, Cz0, s.kz);
+    const float Ax = pick3(Ax0, Ay0, Az0, s.kx) - s.sx * Akz;
+    const float Ay = pick3(Ax0, Ay0, Az0, s.ky) - s.sy * Akz;
+    const float Bx = pick3(Bx0, By0, Bz0, s.kx) - s.sx * Bkz;
+    const float By = pick3(Bx0, By0, Bz0, s.ky) - s.sy * Bkz;
+    const float Cx = pick3(Cx0, Cy0, Cz0, s.kx) - s.sx * Ckz;
+    const float Cy = pick3(Cx0, Cy0, Cz0, s.ky) - s.sy * Ckz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        // exact signs from double products of the FP32 sheared coordinates
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    const float det = U + V + W;
+    if (det == 0.0f) return false;
+    const float T = U * (s.sz * Akz) + V * (s.sz * Bkz) + W * (s.sz * Ckz);
+    const float inv = 1.0f / det;
+    const float tt = T * inv;
+    if (!(tt >= t_lo && tt <= t_hi)) return false;
+    t = tt;
+    u = V * inv;
+    v = W * inv;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// BVH traversal
+// ---------------------------------------------------------------------------
+
+struct BoxRay {
+    float ox, oy, oz, ix, iy, iz;
+};
+
+HYB_HD float safe_inv(float d) {
+    // a zero component becomes a tiny value of the same sign: the slab then
+    // spans +-huge instead of producing 0 * inf = NaN
+    return 1.0f / (fabsf(d) > 1e-30f ? d : copysignf(1e-30f, d));
+}
+
+// Conservative slab test: tn/tf of the box clipped to [lo, hi]; hit iff tn <= tf.
+HYB_HD void box_clip(const BoxRay& r, float lx, float hx, float ly, float hy, float lz, float hz,
+                                         float seg_lo, float seg_hi, float& tn, float& tf) {
+    const float t0x = (lx - r.ox) * r.ix, t1x = (hx - r.ox) * r.ix;
+    const float t0y = (ly - r.oy) * r.iy, t1y = (hy - r.oy) * r.iy;
+    const float t0z = (lz - r.oz) * r.iz, t1z = (hz - r.oz) * r.iz;
+    tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), seg_lo));
+    tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), seg_hi)) * kBoxPad;
+}
+
+struct Hit {
+    float t;
+    int prim;
+    float u, v;
+};
+
+// Closest triangle hit on [seg_lo, seg_hi] (both inclusive).  Equal t goes to
+// the smallest original triangle id, independent of traversal order.
+// `stack` points at this lane's first LDS slot; consecutive entries are
+// `stride` ints apart (one slot per thread of the block, no bank conflicts).
+template <bool COUNT>
+HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                                           float ox, float oy, float oz, float dx, float dy, float dz,
+                                           float seg_lo, float seg_hi, int* stack, int stride, Counters& cnt) {
+    Hit best;
+    best.t = seg_hi;
+    best.prim = -1;
+    best.u = 0.0f;
+    best.v = 0.0f;
+    const BoxRay br = {ox, oy, oz, safe_inv(dx), safe_inv(dy), safe_inv(dz)};
+    const ShearRay sr = make_shear(dx, dy, dz);
+    int spill[kStackDepth - kLdsDepth];
+    int sp = 0;
+    int ref = 0;  // root
+    for (;;) {
+        if (ref >= 0) {
+            const float4* n = nodes + 4 * (int64_t)ref;
+            const float4 a = n[0], b = n[1], c = n[2], e = n[3];
+            if (COUNT) cnt.nodes++;
+            float tn0, tf0, tn1, tf1;
+            const float hi = best.t * kBoxPad;
+            box_clip(br, a.x, a.y, a.z, a.w, c.x, c.y, seg_lo, hi, tn0, tf0);
+            box_clip(br, b.x, b.y, b.z, b.w, c.z, c.w, seg_lo, hi, tn1, tf1);
+            const bool h0 = tn0 <= tf0, h1 = tn1 <= tf1;
+            const int r0 = bits_i(e.x), r1 = bits_i(e.y);
+            if (h0 && h1) {
+                const bool first0 = tn0 <= tn1;
+                const int far = first0 ? r1 : r0;
+                if (sp < kLdsDepth) stack[sp * stride] = far;
+                else spill[sp - kLdsDepth] = far;
+                ++sp;
+                ref = first0 ? r0 : r1;
+                continue;
+            }
+            if (h0) { ref = r0; continue; }
+            if (h1) { ref = r1; continue; }
+        } else {
+            const int info = ~ref;
+            const int first = info >> 3, count = info & 7;
+            for (int k = 0; k < count; ++k) {
+                const float4* tp = tris + 3 * (int64_t)(first + k);
+                const float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
+                if (COUNT) cnt.tris++;
+                float t, u, v;
+                if (tri_hit(sr, ox, oy, oz, v0, v1, v2, seg_lo, best.t, t, u, v)) {
+                    const int id = bits_i(v0.w);
+                    if (t < best.t || best.prim < 0 || id < best.prim) {
+                        best.t = t;
+                        best.prim = id;
+                        best.u = u;
+                        best.v = v;
+                    }
+                }
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        ref = sp < kLdsDepth ? stack[sp * stride] : spill[sp - kLdsDepth];
+    }
+    if (best.prim < 0) best.t = __builtin_inff();
+    return best;
+}
+
+// ---------------------------------------------------------------------------
+// distance field
+// ---------------------------------------------------------------------------
+
+struct Grid {
+    const float* __restrict__ v;  // n^3 samples, x fastest
+    int n;
+    float lo_x, lo_y, lo_z, h, inv_h;
+    float inv_l;    // 1 / Lipschitz bound of the interpolant (slightly reduced)
+    double inv_hd;  // 1 / h in FP64
+};
+
+HYB_HD void corners(const Grid& g, int i, int j, int k, float f[8]) {
+    const int64_t n = g.n;
+    const float* p = g.v + (int64_t)i + n * ((int64_t)j + n * (int64_t)k);
+    const int64_t sy = n, sz = n * n;
+    f[0] = p[0];
+    f[1] = p[1];
+    f[2] = p[sy];
+    f[3] = p[sy + 1];
+    f[4] = p[sz];
+    f[5] = p[sz + 1];
+    f[6] = p[sz + sy];
+    f[7] = p[sz + sy + 1];
+}
+
+HYB_HD float lerp_cell(const float f[8], float x, float y, float z) {
+    const float a = f[0] + x * (f[1] - f[0]);
+    const float b = f[2] + x * (f[3] - f[2]);
+    const float c = f[4] + x * (f[5] - f[4]);
+    const float d = f[6] + x * (f[7] - f[6]);
+    const float e = a + y * (b - a);
+    const float q = c + y * (d - c);
+    return e + z * (q - e);
+}
+
+// Cubic g(s) = k0 + k1 s + k2 s^2 + k3 s^3 of the trilinear interpolant along
+// (x + qx s, y + qy s, z + qz s) inside one cell, from its monomial form
+// f = c0 + cx x + cy y + cz z + cxy xy + cxz xz + cyz yz + cxyz xyz.
+HYB_HD void cell_cubic(const float f[8], float x, float y, float z, float qx, float qy, float qz,
+                                           float k[4]) {
+    const float c0 = f[0];
+    const float cx = f[1] - f[0], cy = f[2] - f[0], cz = f[4] - f[0];
+    const float cxy = f[3] - f[2] - f[1] + f[0];
+    const float cxz = f[5] - f[4] - f[1] + f[0];
+    const float cyz = f[6] - f[4] - f[2] + f[0];
+    const float cxyz = f[7] - f[6] - f[5] - f[3] + f[4] + f[2] + f[1] - f[0];
+    // gradient at s = 0 and mixed second-order terms
+    const float gx = cx + cxy * y + cxz * z + cxyz * y * z;
+    const float gy = cy + cxy * x + cyz * z + cxyz * x * z;
+    const float gz = cz + cxz * x + cyz * y + cxyz * x * y;
+    k[0] = c0 + cx * x + cy * y + cz * z + cxy * x * y + cxz * x * z + cyz * y * z + cxyz * x * y * z;
+    k[1] = gx * qx + gy * qy + gz * qz;
+    k[2] = qx * qy * (cxy + cxyz * z) + qx * qz * (cxz + cxyz * y) + qy * qz * (cyz + cxyz * x);
+    k[3] = cxyz * qx * qy * qz;
+}
+
+HYB_HD float cubic_at(const float k[4], float s) { return fmaf(fmaf(fmaf(k[3], s, k[2]), s, k[1]), s, k[0]); }
+
+// First s in [0, S] with g(s) <= 0, or -1.  g is split into monotone pieces at
+// the roots of g'; the first piece ending at or below zero is bisected.
+HYB_HD float cell_first_root(const float k[4], float S) {
+    if (k[0] <= 0.0f) return 0.0f;
+    if (!(S > 0.0f)) return -1.0f;
+    float r0 = S, r1 = S;
+    const float A = 3.0f * k[3], B = 2.0f * k[2], C = k[1];
+    if (A != 0.0f) {
+        const float disc = B * B - 4.0f * A * C;
+        if (disc >= 0.0f) {
+            const float q = -0.5f * (B + copysignf(sqrtf(disc), B));
+            float a = q / A, b = q != 0.0f ? C / q : S;
+            if (a > b) {
+                float t = a;
+                a = b;
+                b = t;
+            }
+            r0 = (a > 0.0f && a < S) ? a : S;
+            r1 = (b > 0.0f && b < S) ? b : S;
+            if (r0 == S) r0 = r1;
+        }
+    } else if (B != 0.0f) {
+        const float a = -C / B;
+        r0 = r1 = (a > 0.0f && a < S) ? a : S;
+    }
+    const float ends[3] = {r0, r1, S};
+    float lo = 0.0f;
+    for (int e = 0; e < 3; ++e) {
+        const float hi = ends[e];
+        if (hi <= lo && e > 0) continue;
+        if (cubic_at(k, hi) <= 0.0f) {
+            float a = lo, b = hi;
+            for (int it = 0; it < 40; ++it) {
+                const float m = 0.5f * (a + b);
+                if (m <= a || m >= b) break;
+                if (cubic_at(k, m) <= 0.0f) b = m;
+                else a = m;
+            }
+            return b;
+        }
+        lo = hi;
+    }
+    return -1.0f;
+}
+
+// First t in [a, b] (clipped to the grid box) where the trilinear interpolant
+// of the samples is <= 0, or +inf.
+//
+// The ray's position in cell units, X(t) = (o - lo)/h + t d/h, is formed in
+// FP64 (MI355X runs FP64 FMA at half the FP32 rate) so the in-cell fraction
+// X - floor(X) keeps full FP32 precision even tens of cells from the origin;
+// the per-cell cubic and its root are FP32.
+template <bool COUNT>
+HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz, float a,
+                           float b, Counters& cnt) {
+    // clip to the grid box [lo, lo + (n-1) h]^3
+    const float ext = (float)(g.n - 1) * g.h;
+    {
+        const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+        const float t0x = (g.lo_x - ox) * ix, t1x = (g.lo_x + ext - ox) * ix;
+        const float t0y = (g.lo_y - oy) * iy, t1y = (g.lo_y + ext - oy) * iy;
+        const float t0z = (g.lo_z - oz) * iz, t1z = (g.lo_z + ext - oz) * iz;
+        a = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), a));
+        b = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), b));
+        if (!(a <= b)) return __builtin_inff();
+    }
+    const double ih = g.inv_hd;
+    const double px = ((double)ox - (double)g.lo_x) * ih, py = ((double)oy - (double)g.lo_y) * ih,
+                 pz = ((double)oz - (double)g.lo_z) * ih;
+    const double qx = (double)dx * ih, qy = (double)dy * ih, qz = (double)dz * ih;
+    const double iqx = qx != 0.0 ? 1.0 / qx : 0.0, iqy = qy != 0.0 ? 1.0 / qy : 0.0, iqz = qz != 0.0 ? 1.0 / qz : 0.0;
+    const float qxf = (float)qx, qyf = (float)qy, qzf = (float)qz;
+    const int nm2 = g.n - 2;
+    const float band_in = 1.0f * g.h, band_out = 2.0f * g.h;
+    float t = a;
+    float f[8];
+    for (int guard = 0; guard < 16 * g.n + 64; ++guard) {
+        // sphere-tracing phase: the cell of X(t) by floor
+        double X = fma((double)t, qx, px), Y = fma((double)t, qy, py), Z = fma((double)t, qz, pz);
+        int ci = min(max((int)floor(X), 0), nm2);
+        int cj = min(max((int)floor(Y), 0), nm2);
+        int ck = min(max((int)floor(Z), 0), nm2);
+        corners(g, ci, cj, ck, f);
+        if (COUNT) cnt.df++;
+        float fx = (float)(X - ci), fy = (float)(Y - cj), fz = (float)(Z - ck);
+        float val = lerp_cell(f, fx, fy, fz);
+        if (val <= 0.0f) return t;
+        if (val > band_in) {
+            t = fmaf(val, g.inv_l, t);
+            if (t > b) return __builtin_inff();
+            continue;
+        }
+        // near the surface: walk cells in order, exact root of each cell's cubic
+        for (; guard < 16 * g.n + 64; ++guard) {
+            // exit face per axis; an axis the ray does not move along never exits
+            const float ex = qx != 0.0 ? (float)(((qx > 0.0 ? ci + 1 : ci) - px) * iqx) : __builtin_inff();
+            const float ey = qy != 0.0 ? (float)(((qy > 0.0 ? cj + 1 : cj) - py) * iqy) : __builtin_inff();
+            const float ez = qz != 0.0 ? (float)(((qz > 0.0 ? ck + 1 : ck) - pz) * iqz) : __builtin_inff();
+            const float t_exit = fminf(fminf(ex, ey), ez);
+            const float t_end = fminf(t_exit, b);
+            float k[4];
+            cell_cubic(f, fx, fy, fz, qxf, qyf, qzf, k);
+            const float s = cell_first_root(k, t_end - t);
+            if (s >= 0.0f) return t + s;
+            if (t_exit >= b) return __builtin_inff();
+            // step into the neighbour across the exit face
+            if (ex <= ey && ex <= ez) ci += qx > 0.0 ? 1 : -1;
+            else if (ey <= ez) cj += qy > 0.0 ? 1 : -1;
+            else ck += qz > 0.0 ? 1 : -1;
+            if (ci < 0 || cj < 0 || ck < 0 || ci > nm2 || cj > nm2 || ck > nm2) return __builtin_inff();
+            t = fmaxf(t, t_exit);
+            X = fma((double)t, qx, px);
+            Y = fma((double)t, qy, py);
+            Z = fma((double)t, qz, pz);
+            fx = (float)(X - ci);
+            fy = (float)(Y - cj);
+            fz = (float)(Z - ck);
+            corners(g, ci, cj, ck, f);
+            if (COUNT) cnt.df++;
+            val = lerp_cell(f, fx, fy, fz);
+            if (val > band_out) break;  // far enough again: back to sphere steps
+        }
+    }
+    return __builtin_inff();
+}
+
+// Gradient bound of the trilinear interpolant inside one cell (corners f):
+// each partial derivative is a convex blend of the cell's four edge differences
+// along that axis (divided by h), so |grad| <= sqrt(mx^2 + my^2 + mz^2) / h.
+HYB_HD float cell_lipschitz(const float f[8], float inv_h) {
+    const float mx = fmaxf(fmaxf(fabsf(f[1] - f[0]), fabsf(f[3] - f[2])), fmaxf(fabsf(f[5] - f[4]), fabsf(f[7] - f[6])));
+    const float my = fmaxf(fmaxf(fabsf(f[2] - f[0]), fabsf(f[3] - f[1])), fmaxf(fabsf(f[6] - f[4]), fabsf(f[7] - f[5])));
+    const float mz = fmaxf(fmaxf(fabsf(f[4] - f[0]), fabsf(f[5] - f[1])), fmaxf(fabsf(f[6] - f[2]), fabsf(f[7] - f[3])));
+    return sqrtf(mx * mx + my * my + mz * mz) * inv_h;
+}
+
+// Lipschitz bound used for steps, from the largest cell bound of the grid: at
+// least 1 (keeps steps finite on flat fields), rounded up a few ulps so it
+// stays a bound after FP32 evaluation.
+inline float finish_lipschitz(float cell_max) { return fmaxf(cell_max, 1.0f) * (1.0f + 4e-7f); }
+
+// Reciprocal step factor: g * inv_step(L) is a safe sphere-tracing step.
+inline float inv_step(float lipschitz) { return (1.0f / lipschitz) * (1.0f - 1e-6f); }
+
+// One ray of a query (the body of the trace kernels).
+template <int MODE, bool COUNT>
+HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
+    const float ox = a.ox[i], oy = a.oy[i], oz = a.oz[i];
+    const float dx = a.dx[i], dy = a.dy[i], dz = a.dz[i];
+    const float tmin = a.tmin ? a.tmin[i] : 0.0f;
+    Counters cnt;
+    Hit hit;
+    hit.t = __builtin_inff();
+    hit.prim = -1;
+    hit.u = 0.0f;
+    hit.v = 0.0f;
+    if (tmin <= a.tmax) {
+        const Grid g = {a.sdf, a.n_grid, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, 1.0 / (double)a.h};
+        if (MODE == kBvhOnly) {
+            hit = bvh_closest<COUNT>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, a.tmax, stack, stride, cnt);
+        } else if (MODE == kDfOnly) {
+            const float t = df_first_root<COUNT>(g, ox, oy, oz, dx, dy, dz, tmin, a.tmax, cnt);
+            if (t < __builtin_inff()) {
+                hit.t = t;
+                hit.prim = -2;
+            }
+        } else {
+            // Eq. (2) with two sub-queries processed in order (first hit):
+            // triangles on [tmin, t1]; the distance field on [t1, tmax] only
+            // when the first sub-query found nothing.
+            const float t1 = fminf(fmaf(a.tau, a.h, tmin), a.tmax);
+            if (t1 > tmin) hit = bvh_closest<COUNT>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt);
+            if (hit.prim < 0 && (t1 < a.tmax || a.tau == 0.0f)) {
+                const float t = df_first_root<COUNT>(g, ox, oy, oz, dx, dy, dz, t1, a.tmax, cnt);
+                if (t < __builtin_inff()) {
+                    hit.t = t;
+                    hit.prim = -2;
+                }
+            }
+        }
+    }
+    a.t[i] = hit.t;
+    a.prim[i] = hit.prim;
+    a.u[i] = hit.u;
+    a.v[i] = hit.v;
+    if (COUNT) {
+        a.counts[3 * i + 0] = cnt.nodes;
+        a.counts[3 * i + 1] = cnt.tris;
+        a.counts[3 * i + 2] = cnt.df;
+    }
+}
+
+}  // namespace hyb

@@ -1,0 +1,49 @@
+// Launchers of the device kernels (internal header shared by the C API).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hyb {
+
+enum TraceMode : int { kCombined = 0, kBvhOnly = 1, kDfOnly = 2 };
+
+struct TraceArgs {
+    // rays (device SoA)
+    const float *ox, *oy, *oz, *dx, *dy, *dz, *tmin;
+    // hits (device SoA)
+    float* t;
+    int32_t* prim;
+    float *u, *v;
+    int32_t* counts;  // 3 per ray or null
+    // scene
+    const float4* nodes;
+    const float4* tris;
+    const float* sdf;
+    int32_t n_grid;
+    float lo_x, lo_y, lo_z, h, inv_h, inv_l;
+    // query
+    float tmax, tau;
+    int64_t n;
+};
+
+hipError_t launch_trace(int mode, bool counters, const TraceArgs& a, hipStream_t stream);
+
+struct SdfBuildArgs {
+    const float4* nodes;
+    const float4* tris;
+    int32_t n_grid;
+    float lo_x, lo_y, lo_z, h;
+    int32_t exterior_solid;
+    float* out;  // n^3 floats, x fastest
+};
+
+hipError_t launch_sdf_build(const SdfBuildArgs& a, hipStream_t stream);
+
+// Per-block maxima of the cell Lipschitz bounds of an n^3 grid (x fastest)
+// into block_max[0 .. n_blocks); returns n_blocks through *n_blocks.
+hipError_t launch_lipschitz(const float* grid, int32_t n, float h, float* block_max, int32_t* n_blocks,
+                            hipStream_t stream);
+int32_t lipschitz_blocks(int32_t n);
+
+}  // namespace hyb

@@ -1,0 +1,42 @@
+// Trace kernels: the combined query and the two pure baselines.
+//
+// One ray per lane.  Rays and hits are SoA arrays, so each of the seven input
+// and four output streams is read or written with fully coalesced 256-byte
+// wavefront accesses.  The BVH stack lives in LDS ([depth][thread] so the 64
+// lanes of a wavefront hit 64 distinct banks), with a small private spill area
+// for the rare paths deeper than the LDS part.
+#include "hyb_device.hpp"
+#include "kernels.hpp"
+
+namespace hyb {
+
+template <int MODE, bool COUNT>
+__global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a) {
+    extern __shared__ int s_stack[];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.n) return;
+    trace_ray<MODE, COUNT>(a, i, s_stack + threadIdx.x, kBlock);
+}
+
+template <int MODE, bool COUNT>
+static hipError_t launch(const TraceArgs& a, hipStream_t stream) {
+    const int64_t blocks = (a.n + kBlock - 1) / kBlock;
+    const size_t lds = MODE == kDfOnly ? 0 : sizeof(int) * kLdsDepth * kBlock;
+    hipLaunchKernelGGL((k_trace<MODE, COUNT>), dim3((unsigned)blocks), dim3(kBlock), lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(int mode, bool counters, const TraceArgs& a, hipStream_t stream) {
+    if (a.n <= 0) return hipSuccess;
+    switch (mode * 2 + (counters ? 1 : 0)) {
+        case 0: return launch<kCombined, false>(a, stream);
+        case 1: return launch<kCombined, true>(a, stream);
+        case 2: return launch<kBvhOnly, false>(a, stream);
+        case 3: return launch<kBvhOnly, true>(a, stream);
+        case 4: return launch<kDfOnly, false>(a, stream);
+        case 5: return launch<kDfOnly, true>(a, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hyb

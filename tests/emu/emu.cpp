@@ -1,0 +1,112 @@
+// CPU emulation of the library's kernels: runs the exact per-ray trace body and
+// per-node distance-field body on the host, so tests can compare the kernel
+// logic with the oracle (and run it under AddressSanitizer) without a GPU.
+//
+//   emu <input.bin> <output.bin>
+//
+// input:  int64 hdr[8] = {what, n_rays, n_verts, n_tris, N, has_tmin, mode, 0}
+//         float par[8] = {tmax, tau, lo_x, lo_y, lo_z, h, exterior_solid, 0}
+//         verts f32[3 n_verts], tris i32[3 n_tris], grid f32[N^3] (what 0, N > 0),
+//         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays] (has_tmin)
+// what 0 (trace): output t f32[n], prim i32[n], u f32[n], v f32[n], counts i32[3n]
+// what 1 (sdf):   output f32[N^3] signed distances of the grid nodes
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "bvh_build.hpp"
+#include "hyb_device.hpp"
+#include "sdf_device.hpp"
+
+template <class T>
+static std::vector<T> rd(FILE* f, size_t n) {
+    std::vector<T> v(n);
+    if (n && fread(v.data(), sizeof(T), n, f) != n) {
+        fprintf(stderr, "short read\n");
+        exit(2);
+    }
+    return v;
+}
+
+int main(int argc, char** argv) {
+    if (argc != 3) return 2;
+    FILE* f = fopen(argv[1], "rb");
+    if (!f) return 2;
+    auto hdr = rd<long long>(f, 8);
+    auto par = rd<float>(f, 8);
+    const long long what = hdr[0], n = hdr[1], nv = hdr[2], nt = hdr[3], N = hdr[4], has_tmin = hdr[5], mode = hdr[6];
+    auto verts = rd<float>(f, 3 * nv);
+    auto tris = rd<int32_t>(f, 3 * nt);
+    std::vector<float> grid = what == 0 && N > 0 ? rd<float>(f, N * N * N) : std::vector<float>();
+    auto rays = rd<float>(f, 6 * n);
+    auto tmin = has_tmin ? rd<float>(f, n) : std::vector<float>();
+    fclose(f);
+
+    hyb::BvhHost bvh;
+    int rc = hyb::build_bvh_host(verts.data(), nv, tris.data(), nt, &bvh);
+    if (rc) {
+        fprintf(stderr, "bvh build failed %d\n", rc);
+        return 3;
+    }
+    // exact-size device-layout buffers so the sanitizer sees any overrun
+    std::vector<float4> nodes(bvh.nodes.size() / 4), tri4(bvh.tris.size() / 4);
+    for (size_t i = 0; i < nodes.size(); ++i)
+        nodes[i] = make_float4(bvh.nodes[4 * i], bvh.nodes[4 * i + 1], bvh.nodes[4 * i + 2], bvh.nodes[4 * i + 3]);
+    for (size_t i = 0; i < tri4.size(); ++i)
+        tri4[i] = make_float4(bvh.tris[4 * i], bvh.tris[4 * i + 1], bvh.tris[4 * i + 2], bvh.tris[4 * i + 3]);
+
+    FILE* o = fopen(argv[2], "wb");
+    if (!o) return 2;
+    if (what == 1) {
+        std::vector<float> out(N * N * N);
+        for (long long id = 0; id < N * N * N; ++id) {
+            const long long i = id % N, j = (id / N) % N, k = id / (N * N);
+            hyb::D3 p = hyb::d3((double)par[2] + (double)i * (double)par[5], (double)par[3] + (double)j * (double)par[5],
+                                (double)par[4] + (double)k * (double)par[5]);
+            out[id] = (float)hyb::sdf_node_value(tri4.empty() ? nullptr : nodes.data(), tri4.data(), p, (int)par[6]);
+        }
+        fwrite(out.data(), 4, out.size(), o);
+        fclose(o);
+        return 0;
+    }
+    float L = 0.0f;
+    const float inv_h = 1.0f / par[5];
+    for (long long k = 0; k + 1 < N; ++k)
+        for (long long j = 0; j + 1 < N; ++j)
+            for (long long i = 0; i + 1 < N; ++i) {
+                const float* p = grid.data() + i + N * (j + N * k);
+                const float c[8] = {p[0], p[1], p[N], p[N + 1], p[N * N], p[N * N + 1], p[N * N + N], p[N * N + N + 1]};
+                L = fmaxf(L, hyb::cell_lipschitz(c, inv_h));
+            }
+    L = hyb::finish_lipschitz(L);
+
+    std::vector<float> t(n), u(n), v(n);
+    std::vector<int32_t> prim(n), counts(3 * n);
+    hyb::TraceArgs a{};
+    a.ox = rays.data(); a.oy = rays.data() + n; a.oz = rays.data() + 2 * n;
+    a.dx = rays.data() + 3 * n; a.dy = rays.data() + 4 * n; a.dz = rays.data() + 5 * n;
+    a.tmin = has_tmin ? tmin.data() : nullptr;
+    a.t = t.data(); a.prim = prim.data(); a.u = u.data(); a.v = v.data(); a.counts = counts.data();
+    a.nodes = nodes.data();
+    a.tris = tri4.data();
+    a.sdf = grid.empty() ? nullptr : grid.data();
+    a.n_grid = (int)N;
+    a.lo_x = par[2]; a.lo_y = par[3]; a.lo_z = par[4]; a.h = par[5]; a.inv_h = inv_h;
+    a.inv_l = hyb::inv_step(L);
+    a.tmax = par[0];
+    a.tau = par[1];
+    a.n = n;
+    std::vector<int> stack(hyb::kLdsDepth);
+    for (long long i = 0; i < n; ++i) {
+        if (mode == 0) hyb::trace_ray<hyb::kCombined, true>(a, i, stack.data(), 1);
+        else if (mode == 1) hyb::trace_ray<hyb::kBvhOnly, true>(a, i, stack.data(), 1);
+        else hyb::trace_ray<hyb::kDfOnly, true>(a, i, stack.data(), 1);
+    }
+    fwrite(t.data(), 4, n, o);
+    fwrite(prim.data(), 4, n, o);
+    fwrite(u.data(), 4, n, o);
+    fwrite(v.data(), 4, n, o);
+    fwrite(counts.data(), 4, 3 * n, o);
+    fclose(o);
+    return 0;
+}

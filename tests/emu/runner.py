@@ -1,0 +1,86 @@
+"""Build and drive the CPU emulation of the library kernels (tests/emu/emu.cpp).
+
+The emulator compiles the kernels' per-ray and per-node bodies for the host
+(hipcc, host pass only, AddressSanitizer + UBSan on the host code) and runs them
+on the same inputs the GPU path gets.  Test infrastructure only."""
+from __future__ import annotations
+
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2305_07253_amd", "csrc")
+BUILD = os.path.join(HERE, "_build")
+EXE = os.path.join(BUILD, "emu")
+
+
+def build(force: bool = False) -> str:
+    srcs = [os.path.join(HERE, "emu.cpp"), os.path.join(CSRC, "bvh_build.cpp")]
+    deps = srcs + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    if not force and os.path.exists(EXE) and os.path.getmtime(EXE) >= max(os.path.getmtime(d) for d in deps):
+        return EXE
+    os.makedirs(BUILD, exist_ok=True)
+    tmp = EXE + ".tmp%d" % os.getpid()
+    cmd = ["/opt/rocm/bin/hipcc", "-x", "hip", "--offload-host-only", "-O1", "-g", "-std=c++17",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined",
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(r.stdout)
+    os.replace(tmp, EXE)
+    return EXE
+
+
+def _run(hdr, par, arrays, out_bytes):
+    exe = build()
+    with tempfile.TemporaryDirectory() as d:
+        fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
+        with open(fin, "wb") as f:
+            np.asarray(hdr, dtype=np.int64).tofile(f)
+            np.asarray(par, dtype=np.float32).tofile(f)
+            for a in arrays:
+                np.ascontiguousarray(a).tofile(f)
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+        r = subprocess.run([exe, fin, fout], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env)
+        if r.returncode != 0:
+            raise RuntimeError("emulator failed (%d):\n%s" % (r.returncode, r.stdout[-4000:]))
+        data = np.fromfile(fout, dtype=np.uint8)
+        assert len(data) == out_bytes
+        return data
+
+
+def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None):
+    """Returns (t, prim, u, v, counts) exactly as the kernels compute them."""
+    rays_soa = np.ascontiguousarray(rays_soa, dtype=np.float32)
+    n = rays_soa.shape[1]
+    N = 0 if grid is None else np.asarray(grid).shape[-1]
+    g4 = np.zeros(4, np.float32) if grid4 is None else np.asarray(grid4, np.float32)
+    arrays = [np.asarray(verts, np.float32), np.asarray(tris, np.int32)]
+    if N:
+        arrays.append(np.asarray(grid, np.float32))
+    arrays.append(rays_soa)
+    if tmin is not None:
+        arrays.append(np.asarray(tmin, np.float32))
+    hdr = [0, n, len(verts), len(tris), N, tmin is not None, mode, 0]
+    par = [tmax, tau, g4[0], g4[1], g4[2], g4[3], 0, 0]
+    raw = _run(hdr, par, arrays, 4 * n * 7)
+    t = raw[: 4 * n].view(np.float32)
+    prim = raw[4 * n: 8 * n].view(np.int32)
+    u = raw[8 * n: 12 * n].view(np.float32)
+    v = raw[12 * n: 16 * n].view(np.float32)
+    counts = raw[16 * n:].view(np.int32).reshape(n, 3)
+    return t, prim, u, v, counts
+
+
+def sdf(verts, tris, grid4, N, exterior_solid=True):
+    """The distance-field build kernel's node values, (N,N,N) [k,j,i]."""
+    g4 = np.asarray(grid4, np.float32)
+    hdr = [1, 0, len(verts), len(tris), N, 0, 0, 0]
+    par = [0, 0, g4[0], g4[1], g4[2], g4[3], 1.0 if exterior_solid else 0.0, 0]
+    raw = _run(hdr, par, [np.asarray(verts, np.float32), np.asarray(tris, np.int32)], 4 * N ** 3)
+    return raw.view(np.float32).reshape(N, N, N)

@@ -1,0 +1,201 @@
+"""GPU parity: the HIP kernels through the C ABI against the FP64 oracle.
+
+Tiny room (1,052 triangles, 32^3 grid) at every threshold, the pure baselines,
+the distance-field build, ragged and degenerate inputs, and the GI-shaped
+workload (188k triangles, 128^3 grid, 2.07M G-buffer rays) traced in full in
+the launch configuration the benchmark times and compared on a sampled
+subset."""
+import numpy as np
+import pytest
+
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+TAUS = (0.0, 0.5, 1.0, 2.0, 4.0, np.inf)
+
+
+@pytest.fixture(scope="module")
+def hyb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2305_07253_amd as hyb
+    hyb.lib()
+    return hyb
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(out):
+    return [x.cpu().numpy() for x in out]
+
+
+@pytest.fixture(scope="module")
+def tiny_dev(hyb, tiny):
+    sc = tiny["scene"]
+    bvh = hyb.build_bvh(sc.verts, sc.tris)
+    sdf = hyb.sdf_from_grid(to_dev(tiny["grid"].reshape(-1)), tiny["grid4"])
+    return dict(bvh=bvh, sdf=sdf, free=to_dev(tiny["free"].soa()), surf=to_dev(tiny["surf"].soa()))
+
+
+@pytest.mark.parametrize("which", ["free", "surf"])
+@pytest.mark.parametrize("tau", TAUS)
+def test_tiny_combined(hyb, orc, tiny, tiny_dev, which, tau):
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    s = tiny[which].soa()
+    got = host(hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], tiny_dev[which], 2.0, tau))
+    ref = orc.query(sc.verts, sc.tris, grid, g4, s, 2.0, tau)
+    m, c = orc.margin(sc.verts, sc.tris, grid, g4, s, 2.0, tau)
+    st = parity.check(got, ref, m, c, label="gpu tiny %s tau=%s" % (which, tau))
+    print("tiny", which, tau, st)
+
+
+@pytest.mark.parametrize("which", ["free", "surf"])
+def test_tiny_pure_and_limits(hyb, orc, tiny, tiny_dev, which):
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    s = tiny[which].soa()
+    bvh = host(hyb.trace_bvh(tiny_dev["bvh"], tiny_dev[which], 2.0))
+    df = host(hyb.trace_df(tiny_dev["sdf"], tiny_dev[which], 2.0))
+    for got, mode in ((bvh, 1), (df, 2)):
+        ref = orc.query(sc.verts, sc.tris, grid, g4, s, 2.0, 0.0, mode=mode)
+        m, c = orc.margin(sc.verts, sc.tris, grid, g4, s, 2.0, 0.0, mode=mode)
+        parity.check(got, ref, m, c, label="gpu pure mode %d" % mode)
+    # threshold 0 / +inf equal the pure kernels bit for bit
+    c0 = host(hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], tiny_dev[which], 2.0, 0.0))
+    ci = host(hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], tiny_dev[which], 2.0, np.inf))
+    for a, b in zip(c0, df):
+        assert np.array_equal(a, b)
+    for a, b in zip(ci, bvh):
+        assert np.array_equal(a, b)
+
+
+def test_tiny_counters_early_exit(hyb, tiny_dev):
+    (t, prim, u, v), cnt = hyb.trace_counters(tiny_dev["bvh"], tiny_dev["sdf"], tiny_dev["surf"], 2.0, 2.0)
+    prim, cnt = prim.cpu().numpy(), cnt.cpu().numpy()
+    assert (prim >= 0).sum() > 100
+    assert np.all(cnt[prim >= 0, 2] == 0)  # first hit in order: no DF work after a triangle hit
+    assert np.all(cnt[prim == -2, 2] > 0)
+    plain = host(hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], tiny_dev["surf"], 2.0, 2.0))
+    assert np.array_equal(plain[1], prim)
+
+
+def test_tiny_sdf_build(hyb, tiny):
+    """hyb_build_sdf (FP64 on the GPU) against the oracle's exact grid."""
+    sc, g4 = tiny["scene"], tiny["grid4"]
+    bvh = hyb.build_bvh(sc.verts, sc.tris)
+    sdf = hyb.build_sdf(bvh, 32, g4, exterior_solid=True)
+    got = hyb.sdf_read(sdf).cpu().numpy()
+    ref = tiny["grid"]
+    ulp = np.maximum(np.spacing(np.abs(ref).astype(np.float32)), 1e-15)
+    assert np.all(np.abs(got.astype(np.float64) - ref) <= ulp)
+    far = np.abs(ref) > 1e-6
+    assert np.array_equal(np.sign(got[far]), np.sign(ref[far]))
+    assert abs(sdf.lipschitz - orc_lipschitz(tiny)) <= 1e-5
+
+
+def orc_lipschitz(tiny):
+    import oracle
+    return oracle.lipschitz(tiny["grid"], np.float64(tiny["grid4"][3]))
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 255, 257, 1000])
+def test_ragged_sizes(hyb, orc, tiny, tiny_dev, n):
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    r = tiny["surf"].subset(slice(0, n))
+    got = host(hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], to_dev(r.soa()), 2.0, 1.0))
+    ref = orc.query(sc.verts, sc.tris, grid, g4, r.soa(), 2.0, 1.0)
+    m, c = orc.margin(sc.verts, sc.tris, grid, g4, r.soa(), 2.0, 1.0)
+    parity.check(got, ref, m, c, label="ragged %d" % n, max_excluded=1.0)
+
+
+def test_edge_arguments(hyb, orc, tiny, tiny_dev):
+    import torch
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    empty = torch.zeros((6, 0), dtype=torch.float32, device="cuda")
+    out = hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], empty, 1.0, 1.0)  # n = 0: no-op
+    assert out[0].numel() == 0
+    with pytest.raises(ValueError):
+        hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], tiny_dev["free"], float("nan"), 1.0)
+    with pytest.raises(ValueError):
+        hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], tiny_dev["free"], 1.0, -1.0)
+    # per-ray tmin, including tmin > tmax (a miss, not an error), and tmax = +inf
+    r = tiny["free"].subset(slice(0, 512))
+    tmin = np.linspace(0.0, 2.5, 512).astype(np.float32)
+    for tmax in (2.0, np.inf):
+        got = host(hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], to_dev(r.soa()), tmax, 1.0, tmin=to_dev(tmin)))
+        ref = orc.query(sc.verts, sc.tris, grid, g4, r.soa(), tmax, 1.0, tmin=tmin)
+        m, c = orc.margin(sc.verts, sc.tris, grid, g4, r.soa(), tmax, 1.0, tmin=tmin)
+        parity.check(got, ref, m, c, label="tmin tmax=%s" % tmax, max_excluded=0.1)
+    got = host(hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], to_dev(r.soa()), 2.0, 1.0, tmin=to_dev(tmin)))
+    assert np.all(got[1][tmin > 2.0] == -1)
+
+
+def test_empty_and_degenerate_meshes(hyb, orc):
+    rng = np.random.default_rng(3)
+    o = rng.uniform(0, 1, (300, 3)).astype(np.float32)
+    d = rng.normal(size=(300, 3)).astype(np.float32)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    s = np.ascontiguousarray(np.concatenate([o.T, d.T]).astype(np.float32))
+    bvh = hyb.build_bvh(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32))
+    got = host(hyb.trace_bvh(bvh, to_dev(s), 10.0))
+    assert np.all(got[1] == -1) and np.all(np.isinf(got[0]))
+    # a degenerate (zero-area) triangle is never hit; a real one is
+    v = np.array([[0.2, 0.2, 0.5], [0.8, 0.3, 0.5], [0.4, 0.9, 0.5], [0.5, 0.5, 0.5]], np.float32)
+    tris = np.array([[0, 1, 2], [3, 3, 3], [0, 0, 1]], np.int32)
+    bvh = hyb.build_bvh(v, tris)
+    got = host(hyb.trace_bvh(bvh, to_dev(s), 10.0))
+    ref = orc.query(v, tris, None, None, s, 10.0, np.inf, mode=1)
+    m, c = orc.margin(v, tris, None, None, s, 10.0, np.inf, mode=1)
+    parity.check(got, ref, m, c, label="degenerate", max_excluded=0.2)
+    assert set(np.unique(got[1])) <= {-1, 0}
+
+
+# ---------------------------------------------------------------------------
+# GI-shaped workload: full size on the GPU, sampled rays against the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def gi(hyb, orc):
+    from paper_2305_07253_amd import workloads as W
+    sc = W.gi_scene(2)
+    g4 = W.room_grid(128)
+    gb = W.gbuffer(sc, 1920, 1080)
+    rays = W.gbuffer_rays(gb, 21)
+    bvh = hyb.build_bvh(sc.verts, sc.tris)
+    sdf = hyb.build_sdf(bvh, 128, g4, exterior_solid=True)
+    sample = np.arange(0, rays.n, 32 * 16)  # 4,050 rays, fixed stride in tile order
+    print("building the oracle's exact 128^3 grid", flush=True)
+    oracle_grid = orc.sdf_grid(sc, g4, 128)
+    return dict(scene=sc, g4=g4, rays=rays, bvh=bvh, sdf=sdf, dev=to_dev(rays.soa()), sample=sample,
+                oracle_grid=oracle_grid)
+
+
+def test_gi_sdf_build_all_nodes(hyb, orc, gi):
+    """Every node of the GPU-built 128^3 grid against the oracle's exact grid."""
+    got = hyb.sdf_read(gi["sdf"]).cpu().numpy()
+    ref = gi["oracle_grid"]
+    ulp = np.maximum(np.spacing(np.abs(ref).astype(np.float32)), 1e-15)
+    bad = np.abs(got.astype(np.float64) - ref.astype(np.float64)) > ulp
+    assert bad.sum() == 0, (bad.sum(), np.argwhere(bad)[:5])
+    far = np.abs(ref) > 1e-6
+    assert np.array_equal(np.sign(got[far]), np.sign(ref[far]))
+
+
+@pytest.mark.parametrize("tau", [0.0, 1.0, 4.0, np.inf])
+def test_gi_full_launch_sampled_parity(hyb, orc, gi, tau):
+    """All 2,073,600 rays traced in one launch through the GPU-built grid;
+    4,050 of them (fixed stride in tile order) against the oracle on its own
+    exact grid."""
+    sc, g4 = gi["scene"], gi["g4"]
+    out = hyb.trace(gi["bvh"], gi["sdf"], gi["dev"], 0.5, tau)
+    got = [x.cpu().numpy()[gi["sample"]] for x in out]
+    sub = gi["rays"].subset(gi["sample"])
+    grid = gi["oracle_grid"]
+    ref = orc.query(sc.verts, sc.tris, grid, g4, sub.soa(), 0.5, tau)
+    m, c = orc.margin(sc.verts, sc.tris, grid, g4, sub.soa(), 0.5, tau)
+    st = parity.check(got, ref, m, c, label="gi tau=%s" % tau)
+    print("gi", tau, st)

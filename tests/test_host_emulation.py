@@ -1,0 +1,99 @@
+"""The library's kernel bodies, compiled for the host (with AddressSanitizer and
+UBSan on), against the FP64 oracle on the tiny room at every threshold.  This
+checks the kernel logic and its memory accesses without a GPU; the GPU tests
+repeat the comparison on the device."""
+import numpy as np
+import pytest
+
+from tests.emu import runner
+from tests import parity
+
+TAUS = (0.0, 0.5, 1.0, 2.0, 4.0, np.inf)
+
+
+@pytest.fixture(scope="module")
+def emu():
+    runner.build()
+    return runner
+
+
+@pytest.mark.parametrize("which", ["free", "surf"])
+@pytest.mark.parametrize("tau", TAUS)
+def test_combined_matches_oracle(emu, orc, tiny, which, tau):
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    rays = tiny[which]
+    got = emu.trace(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, tau)
+    ref = orc.query(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, tau)
+    m, c = orc.margin(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, tau)
+    parity.check(got, ref, m, c, label="emu %s tau=%s" % (which, tau))
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_pure_modes_match_oracle(emu, orc, tiny, mode):
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    for rays in (tiny["free"], tiny["surf"]):
+        got = emu.trace(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, 0.0, mode=mode)
+        ref = orc.query(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, 0.0, mode=mode)
+        m, c = orc.margin(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, 0.0, mode=mode)
+        parity.check(got, ref, m, c, label="emu mode %d" % mode)
+
+
+def test_limits_equal_pure_kernels(emu, tiny):
+    """threshold 0 is DF-only and +inf is BVH-only, bit for bit."""
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    s = tiny["surf"].soa()
+    for tau, mode in ((0.0, 2), (np.inf, 1)):
+        a = emu.trace(sc.verts, sc.tris, grid, g4, s, 2.0, tau, mode=0)
+        b = emu.trace(sc.verts, sc.tris, grid, g4, s, 2.0, tau, mode=mode)
+        for x, y in zip(a[:4], b[:4]):
+            assert np.array_equal(x, y)
+
+
+def test_early_exit_takes_no_df_steps(emu, tiny):
+    """First-hit in order: a ray caught by the triangle segment never touches
+    the distance field."""
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    t, prim, u, v, cnt = emu.trace(sc.verts, sc.tris, grid, g4, tiny["surf"].soa(), 2.0, 2.0)
+    assert (prim >= 0).sum() > 100
+    assert np.all(cnt[prim >= 0, 2] == 0)
+    assert np.all(cnt[prim == -2, 2] > 0)
+
+
+def test_tmin_and_empty_interval(emu, orc, tiny):
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    r = tiny["free"].subset(slice(0, 512))
+    tmin = np.linspace(0.0, 2.5, 512).astype(np.float32)  # tail has tmin > tmax
+    for mode, tau in ((0, 1.0), (1, np.inf), (2, 0.0)):
+        got = emu.trace(sc.verts, sc.tris, grid, g4, r.soa(), 2.0, tau, mode=mode, tmin=tmin)
+        ref = orc.query(sc.verts, sc.tris, grid, g4, r.soa(), 2.0, tau, mode=mode, tmin=tmin)
+        m, c = orc.margin(sc.verts, sc.tris, grid, g4, r.soa(), 2.0, tau, mode=mode, tmin=tmin)
+        parity.check(got, ref, m, c, label="emu tmin mode %d" % mode)
+        assert np.all(got[1][tmin > 2.0] == -1)
+
+
+def test_empty_mesh_and_single_triangle(emu, orc):
+    rng = np.random.default_rng(3)
+    o = rng.uniform(0, 1, (64, 3)).astype(np.float32)
+    d = rng.normal(size=(64, 3)).astype(np.float32)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    s = np.ascontiguousarray(np.concatenate([o.T, d.T]).astype(np.float32))
+    got = emu.trace(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32), None, None, s, 10.0, np.inf, mode=1)
+    assert np.all(got[1] == -1)
+    v = np.array([[0.2, 0.2, 0.5], [0.8, 0.3, 0.5], [0.4, 0.9, 0.5]], np.float32)
+    got = emu.trace(v, [[0, 1, 2]], None, None, s, 10.0, np.inf, mode=1)
+    ref = orc.query(v, [[0, 1, 2]], None, None, s, 10.0, np.inf, mode=1)
+    m, c = orc.margin(v, np.array([[0, 1, 2]]), None, None, s, 10.0, np.inf, mode=1)
+    parity.check(got, ref, m, c, label="single triangle")
+
+
+def test_sdf_build_matches_oracle(emu, orc, tiny):
+    """The build kernel's exact distance (FP64 -> FP32) against the oracle's:
+    within one FP32 ulp (nodes lying on a surface: within 1e-15 of zero), same
+    sign wherever |f| > 1e-6."""
+    sc, g4 = tiny["scene"], tiny["grid4"]
+    got = emu.sdf(sc.verts, sc.tris, g4, 32)
+    ref = tiny["grid"]
+    ulp = np.maximum(np.spacing(np.abs(ref).astype(np.float32)), 1e-15)
+    assert np.all(np.abs(got.astype(np.float64) - ref) <= ulp)
+    far = np.abs(ref) > 1e-6
+    assert np.array_equal(np.sign(got[far]), np.sign(ref[far]))
