@@ -71,6 +71,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--reps", type=int, default=10, help="launches per sweep point")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="rays for the CPU oracle baseline (0: skip)")
+    ap.add_argument("--tau", type=float, default=None,
+                    help="fix the threshold (voxels) instead of selecting it at the fixed artefact rate")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiling driver: a 256 MiB copy probe, then --steps launches of the combined, "
+                         "triangle-only and DF-only kernels; no sweep, no JSON line")
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     args = ap.parse_args()
@@ -116,6 +121,20 @@ def main():
     out = hyb.alloc_hits(n)
     o_np, d_np = rays.o.astype(np.float64), rays.d.astype(np.float64)
 
+    if args.profile:
+        tau = 0.0 if args.tau is None else args.tau
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB copy probe
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        for name, fn in (("combined", lambda: hyb.trace(bvh, sdf128, R, TMAX, tau, out=out)),
+                         ("bvh_only", lambda: hyb.trace_bvh(bvh, R, TMAX, out=out)),
+                         ("df_only", lambda: hyb.trace_df(sdf128, R128, TMAX, out=out))):
+            ms = time_launches(fn, stream, args.steps, args.warmup)
+            log("%s: %.4f ms per launch (%d rays)" % (name, ms, n))
+        torch.cuda.synchronize()
+        return
+
     # triangle-only reference and timing
     ms_bvh = time_launches(lambda: hyb.trace_bvh(bvh, R, TMAX, out=out), stream, args.reps, 2)
     ref_t, ref_p = out[0].cpu().numpy().astype(np.float64), out[1].cpu().numpy()
@@ -138,6 +157,8 @@ def main():
 
     target = df_only["df256"]["rate"]
     chosen = next((s for s in sweep if s["rate"] <= target), sweep[-1])
+    if args.tau is not None:
+        chosen = next((s for s in sweep if s["tau"] == (args.tau if math.isfinite(args.tau) else "inf")), chosen)
     tau = math.inf if chosen["tau"] == "inf" else chosen["tau"]
 
     # work counters at the chosen threshold -> algorithmic bytes per ray
@@ -167,15 +188,21 @@ def main():
         oracle.build()
         log("oracle grid 128^3 (setup, untimed)")
         og = oracle.sdf_grid(scene, g128, 128)
-        idx = np.linspace(0, n - 1, args.cpu_sample).astype(np.int64)
-        sub = rays.subset(idx)
-        t0 = time.time()
-        oracle.query(scene.verts, scene.tris, og, g128, sub.soa(), TMAX, tau)
-        el = time.time() - t0
+        # grow a fixed-stride sample until it holds about 15 s of oracle work
+        m = args.cpu_sample
+        while True:
+            idx = np.linspace(0, n - 1, m).astype(np.int64)
+            sub = rays.subset(idx)
+            t0 = time.time()
+            oracle.query(scene.verts, scene.tris, og, g128, sub.soa(), TMAX, tau)
+            el = time.time() - t0
+            if el >= 10.0 or m >= n:
+                break
+            m = int(min(n, max(2 * m, m * 15.0 / max(el, 1e-3))))
         cpu = dict(value=sub.n / el / 1e6, unit="Mrays/s", cores=oracle.threads(), kind="oracle",
-                   sample="%d rays at a fixed stride over the tile-ordered G-buffer rays, combined query at "
-                          "threshold %s, brute force over all %d triangles, FP64" % (sub.n, chosen["tau"],
-                                                                                  scene.n_tris))
+                   sample="%d of the %d rays at a fixed stride over the tile-ordered G-buffer rays (%.1f s), "
+                          "combined query at threshold %s, brute force over all %d triangles, FP64" % (
+                              sub.n, n, el, chosen["tau"], scene.n_tris))
         log("cpu oracle: %.4f Mrays/s (%.1fs, %d threads)" % (cpu["value"], el, cpu["cores"]))
 
     line = {

@@ -84,6 +84,14 @@ typedef struct {
  * enclosed by an inward-facing room). */
 #define HYB_SDF_EXTERIOR_SOLID 1u
 
+/* hyb_sdf_from_grid flag: the caller certifies that every sample is the FP32
+ * rounding of one 1-Lipschitz function (an exact distance field, e.g. samples
+ * of a true signed distance).  The tracer then also steps by g - 2E (E the
+ * trilinear interpolation error bound, sqrt(3)/2 h) where that is longer than
+ * g / L.  Grids from hyb_build_sdf carry this property implicitly.  A false
+ * certification can make the tracer pass a root. */
+#define HYB_SDF_LIPSCHITZ_SAMPLES 2u
+
 /* Build a BVH over an indexed triangle mesh (the structure the paper's
  * hardware ray tracing traverses, Section 3).
  *   verts  host, n_verts x 3 floats (x,y,z)
@@ -115,11 +123,14 @@ hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t fl
                          void* stream, hyb_sdf* out);
 
 /* Wrap caller-provided samples as a distance field (copied).
- *   values  device, n^3 floats, x fastest: values[i + n (j + n k)]
+ *   values  device, n^3 floats, x fastest: values[i + n (j + n k)]; 2 <= n <= 1024
  *   grid4   host, {lo_x, lo_y, lo_z, h}
- * The Lipschitz bound used for safe steps is recomputed from the values. */
-hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4, hyb_sdf_format fmt,
-                             void* stream, hyb_sdf* out);
+ *   flags   0 or HYB_SDF_LIPSCHITZ_SAMPLES
+ * The Lipschitz bound used for safe steps is recomputed from the values.
+ * Errors: HYB_ERR_INVALID_ARG for NULL values/grid4/out, bad n, h <= 0,
+ * non-finite grid4 or unknown flags. */
+hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4, uint32_t flags,
+                             hyb_sdf_format fmt, void* stream, hyb_sdf* out);
 
 /* Grid placement, resolution and the Lipschitz bound L of the trilinear
  * interpolant of the stored samples (steps of g/L never pass a root). */

@@ -28,6 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libhyb.so")
 HYB_MISS = -1
 HYB_DF_HIT = -2
 EXTERIOR_SOLID = 1
+LIPSCHITZ_SAMPLES = 2
 SDF_F32, SDF_F16, SDF_I8_BRICK = 0, 1, 2
 MODE_COMBINED, MODE_BVH, MODE_DF = 0, 1, 2
 
@@ -65,7 +66,7 @@ def lib() -> ctypes.CDLL:
             "hyb_build_bvh": [P, i64, P, i64, P, PP],
             "hyb_bvh_info": [P, P, P, P],
             "hyb_build_sdf": [P, i32, P, u32, i32, P, PP],
-            "hyb_sdf_from_grid": [P, i32, P, i32, P, PP],
+            "hyb_sdf_from_grid": [P, i32, P, u32, i32, P, PP],
             "hyb_sdf_info": [P, P, P, P],
             "hyb_sdf_read": [P, P, P],
             "hyb_trace": [P, P, P, i64, f32, f32, P, P],
@@ -176,8 +177,10 @@ def build_sdf(bvh: Bvh, n: int, grid4=None, exterior_solid: bool = True, fmt: in
     return Sdf(out)
 
 
-def sdf_from_grid(values, grid4, fmt: int = SDF_F32, stream=None) -> Sdf:
-    """Wrap a CUDA float32 tensor of n^3 samples (x fastest) as a grid."""
+def sdf_from_grid(values, grid4, lipschitz_samples: bool = False, fmt: int = SDF_F32, stream=None) -> Sdf:
+    """Wrap a CUDA float32 tensor of n^3 samples (x fastest) as a grid.
+    lipschitz_samples certifies the samples are FP32 roundings of a
+    1-Lipschitz function (exact distances), which allows longer steps."""
     torch = _torch()
     if not (values.is_cuda and values.dtype == torch.float32 and values.is_contiguous()):
         raise ValueError("values must be a contiguous float32 CUDA tensor")
@@ -186,8 +189,9 @@ def sdf_from_grid(values, grid4, fmt: int = SDF_F32, stream=None) -> Sdf:
         raise ValueError("values must hold n^3 samples")
     g = np.ascontiguousarray(grid4, dtype=np.float32)
     out = ctypes.c_void_p()
-    _check("hyb_sdf_from_grid", lib().hyb_sdf_from_grid(_ptr(values), n, g.ctypes.data_as(ctypes.c_void_p), fmt,
-                                                        _stream(stream), ctypes.byref(out)))
+    _check("hyb_sdf_from_grid", lib().hyb_sdf_from_grid(
+        _ptr(values), n, g.ctypes.data_as(ctypes.c_void_p), LIPSCHITZ_SAMPLES if lipschitz_samples else 0, fmt,
+        _stream(stream), ctypes.byref(out)))
     return Sdf(out)
 
 

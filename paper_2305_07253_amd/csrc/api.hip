@@ -28,6 +28,7 @@ struct hyb_sdf_s {
     int32_t n = 0;
     float grid4[4] = {0, 0, 0, 0};
     float lipschitz = 0.0f;
+    bool certified = false;  // samples are FP32 roundings of a 1-Lipschitz function
     hyb_sdf_format fmt = HYB_SDF_F32;
 };
 
@@ -106,6 +107,7 @@ void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s) {
         a.h = s->grid4[3];
         a.inv_h = 1.0f / s->grid4[3];
         a.inv_l = hyb::inv_step(s->lipschitz);
+        a.two_e = s->certified ? hyb::certified_slack(s->grid4[3], s->n) : __builtin_inff();
     }
 }
 
@@ -203,6 +205,7 @@ hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t fl
     s->device = bvh->device;
     s->n = n;
     s->fmt = fmt;
+    s->certified = true;  // exact distances to the mesh
     std::memcpy(s->grid4, g4, sizeof(g4));
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t bytes = sizeof(float) * static_cast<size_t>(n) * n * n;
@@ -230,11 +233,12 @@ hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t fl
     return HYB_OK;
 }
 
-hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4, hyb_sdf_format fmt, void* stream,
-                             hyb_sdf* out) {
+hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4, uint32_t flags, hyb_sdf_format fmt,
+                             void* stream, hyb_sdf* out) {
     if (!out) return HYB_ERR_INVALID_ARG;
     *out = nullptr;
-    if (!values || n < 2 || n > 1024 || !valid_grid4(grid4)) return HYB_ERR_INVALID_ARG;
+    if (!values || n < 2 || n > 1024 || !valid_grid4(grid4) || (flags & ~HYB_SDF_LIPSCHITZ_SAMPLES))
+        return HYB_ERR_INVALID_ARG;
     if (fmt != HYB_SDF_F32) return HYB_ERR_UNSUPPORTED;
     hyb_sdf_s* s = new (std::nothrow) hyb_sdf_s;
     if (!s) return HYB_ERR_OOM;
@@ -242,6 +246,7 @@ hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4,
     hipError_t e = hipGetDevice(&s->device);
     s->n = n;
     s->fmt = fmt;
+    s->certified = (flags & HYB_SDF_LIPSCHITZ_SAMPLES) != 0;
     std::memcpy(s->grid4, grid4, sizeof(s->grid4));
     const size_t bytes = sizeof(float) * static_cast<size_t>(n) * n * n;
     if (e == hipSuccess) e = hipMalloc(&s->values, bytes);

@@ -207,6 +207,7 @@ struct Grid {
     int n;
     float lo_x, lo_y, lo_z, h, inv_h;
     float inv_l;    // 1 / Lipschitz bound of the interpolant (slightly reduced)
+    float two_e;    // 2 x (interpolation error bound + storage error), +inf if uncertified
     double inv_hd;  // 1 / h in FP64
 };
 
@@ -257,20 +258,59 @@ HYB_HD void cell_cubic(const float f[8], float x, float y, float z, float qx, fl
 
 HYB_HD float cubic_at(const float k[4], float s) { return fmaf(fmaf(fmaf(k[3], s, k[2]), s, k[1]), s, k[0]); }
 
-// First s in [0, S] with g(s) <= 0, or -1.  g is split into monotone pieces at
-// the roots of g'; the first piece ending at or below zero is bisected.
+// Approximate reciprocal (about 1 ulp) where it only places a guess inside a
+// bracket; exact division in the CPU build of these functions.
+HYB_HD float approx_rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+HYB_HD float cubic_slope(const float k[4], float s) { return fmaf(fmaf(3.0f * k[3], s, 2.0f * k[2]), s, k[1]); }
+
+// Root of the cubic inside (a, b] where g(a) > 0 >= g(b) and g is monotone
+// there: Newton from the secant guess, any step leaving the bracket replaced by
+// bisection, until the step or the bracket is below `tol`.
+HYB_HD float refine_root(const float k[4], float a, float b, float tol) {
+    const float fa = cubic_at(k, a), fb = cubic_at(k, b);
+    float x = b - fb * (b - a) * approx_rcp(fb - fa);
+    if (!(x > a && x <= b)) x = 0.5f * (a + b);
+    for (int it = 0; it < 16; ++it) {
+        const float fx = cubic_at(k, x);
+        if (fx <= 0.0f) b = x;
+        else a = x;
+        if (b - a <= tol) return b;
+        float nx = x - fx * approx_rcp(cubic_slope(k, x));
+        if (fabsf(nx - x) <= tol) return fminf(fmaxf(nx, a), b);
+        if (!(nx > a && nx <= b)) nx = 0.5f * (a + b);
+        x = nx;
+    }
+    return b;
+}
+
+// First s in (0, S] with g(s) <= 0 given g(0) > 0, or -1.
+// Exact rejection first: on [0, S] the cubic is a blend of its four Bernstein
+// coefficients, so if they are all positive g stays positive.  Otherwise g is
+// split into monotone pieces at the roots of g'; the first piece ending at or
+// below zero holds the first root.
 HYB_HD float cell_first_root(const float k[4], float S) {
-    if (k[0] <= 0.0f) return 0.0f;
     if (!(S > 0.0f)) return -1.0f;
+    const float k1 = k[1] * S, k2 = k[2] * S * S, k3 = k[3] * S * S * S;
+    const float b1 = fmaf(k1, 1.0f / 3.0f, k[0]);
+    const float b2 = fmaf(k2, 1.0f / 3.0f, fmaf(k1, 2.0f / 3.0f, k[0]));
+    const float b3 = k[0] + k1 + k2 + k3;
+    if (b1 > 0.0f && b2 > 0.0f && b3 > 0.0f) return -1.0f;
     float r0 = S, r1 = S;
     const float A = 3.0f * k[3], B = 2.0f * k[2], C = k[1];
     if (A != 0.0f) {
         const float disc = B * B - 4.0f * A * C;
         if (disc >= 0.0f) {
             const float q = -0.5f * (B + copysignf(sqrtf(disc), B));
-            float a = q / A, b = q != 0.0f ? C / q : S;
+            float a = q * approx_rcp(A), b = q != 0.0f ? C * approx_rcp(q) : S;
             if (a > b) {
-                float t = a;
+                const float t = a;
                 a = b;
                 b = t;
             }
@@ -279,106 +319,147 @@ HYB_HD float cell_first_root(const float k[4], float S) {
             if (r0 == S) r0 = r1;
         }
     } else if (B != 0.0f) {
-        const float a = -C / B;
+        const float a = -C * approx_rcp(B);
         r0 = r1 = (a > 0.0f && a < S) ? a : S;
     }
-    const float ends[3] = {r0, r1, S};
-    float lo = 0.0f;
-    for (int e = 0; e < 3; ++e) {
-        const float hi = ends[e];
-        if (hi <= lo && e > 0) continue;
-        if (cubic_at(k, hi) <= 0.0f) {
-            float a = lo, b = hi;
-            for (int it = 0; it < 40; ++it) {
-                const float m = 0.5f * (a + b);
-                if (m <= a || m >= b) break;
-                if (cubic_at(k, m) <= 0.0f) b = m;
-                else a = m;
-            }
-            return b;
-        }
-        lo = hi;
+    // first piece whose end is at or below zero
+    float lo = 0.0f, hi = S;
+    if (cubic_at(k, r0) <= 0.0f) hi = r0;
+    else if (r1 > r0 && cubic_at(k, r1) <= 0.0f) {
+        lo = r0;
+        hi = r1;
+    } else if (b3 <= 0.0f) {
+        lo = r1;
+    } else {
+        return -1.0f;
     }
-    return -1.0f;
+    return refine_root(k, lo, hi, 1e-6f * S);
 }
+
+// Marching state of one ray (see df_first_root).
+struct DfRay {
+    double px, py, pz;  // origin in cell units, (o - lo) / h
+    double qx, qy, qz;  // direction in cell units, d / h
+    float qxf, qyf, qzf;
+    float ix, iy, iz;   // time to cross one cell along each axis (inf if not moving)
+    float t, b;         // current position and segment end
+    int ci, cj, ck;     // current cell while walking
+    bool walk;
+};
+
+enum DfStatus : int { kDfContinue = 0, kDfHit = 1, kDfMiss = 2 };
+
+// Clips [a, b] to the grid box and prepares the marching state; false when the
+// segment misses the box.
+HYB_HD bool df_init(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz, float a, float b,
+                    DfRay& r) {
+    const float ext = (float)(g.n - 1) * g.h;
+    const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+    const float t0x = (g.lo_x - ox) * ix, t1x = (g.lo_x + ext - ox) * ix;
+    const float t0y = (g.lo_y - oy) * iy, t1y = (g.lo_y + ext - oy) * iy;
+    const float t0z = (g.lo_z - oz) * iz, t1z = (g.lo_z + ext - oz) * iz;
+    a = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), a));
+    b = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), b));
+    if (!(a <= b)) return false;
+    const double ih = g.inv_hd;
+    r.px = ((double)ox - (double)g.lo_x) * ih;
+    r.py = ((double)oy - (double)g.lo_y) * ih;
+    r.pz = ((double)oz - (double)g.lo_z) * ih;
+    r.qx = (double)dx * ih;
+    r.qy = (double)dy * ih;
+    r.qz = (double)dz * ih;
+    r.qxf = (float)r.qx;
+    r.qyf = (float)r.qy;
+    r.qzf = (float)r.qz;
+    r.ix = r.qxf != 0.0f ? 1.0f / fabsf(r.qxf) : __builtin_inff();
+    r.iy = r.qyf != 0.0f ? 1.0f / fabsf(r.qyf) : __builtin_inff();
+    r.iz = r.qzf != 0.0f ? 1.0f / fabsf(r.qzf) : __builtin_inff();
+    r.t = a;
+    r.b = b;
+    r.ci = r.cj = r.ck = 0;
+    r.walk = false;
+    return true;
+}
+
+// One iteration of the march: fetch the 8 corners of one cell, then either a
+// sphere step or a cell step (see df_first_root).  On kDfHit the hit is r.t.
+template <bool COUNT>
+HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
+    const int nm2 = g.n - 2;
+    const double X = fma((double)r.t, r.qx, r.px), Y = fma((double)r.t, r.qy, r.py), Z = fma((double)r.t, r.qz, r.pz);
+    if (!r.walk) {
+        r.ci = min(max((int)floor(X), 0), nm2);
+        r.cj = min(max((int)floor(Y), 0), nm2);
+        r.ck = min(max((int)floor(Z), 0), nm2);
+    }
+    const float fx = (float)(X - r.ci), fy = (float)(Y - r.cj), fz = (float)(Z - r.ck);
+    float f[8];
+    corners(g, r.ci, r.cj, r.ck, f);
+    if (COUNT) cnt.df++;
+    const float val = lerp_cell(f, fx, fy, fz);
+    if (val <= 0.0f) return kDfHit;
+    if (val > (r.walk ? 2.0f * g.h : g.h)) {
+        r.walk = false;
+        r.t += fmaxf(val * g.inv_l, val - g.two_e);
+        return r.t > r.b ? kDfMiss : kDfContinue;
+    }
+    r.walk = true;
+    // span of the ray inside the current cell, from the in-cell fractions
+    const float ex = (r.qxf > 0.0f ? 1.0f - fx : fx) * r.ix;
+    const float ey = (r.qyf > 0.0f ? 1.0f - fy : fy) * r.iy;
+    const float ez = (r.qzf > 0.0f ? 1.0f - fz : fz) * r.iz;
+    const float t_exit = r.t + fmaxf(fminf(fminf(ex, ey), ez), 0.0f);
+    const float fmin = fminf(fminf(fminf(f[0], f[1]), fminf(f[2], f[3])), fminf(fminf(f[4], f[5]), fminf(f[6], f[7])));
+    if (fmin <= 0.0f) {
+        // some corner at or below zero: exact first root of this cell's cubic
+        float k[4];
+        cell_cubic(f, fx, fy, fz, r.qxf, r.qyf, r.qzf, k);
+        const float s = cell_first_root(k, fminf(t_exit, r.b) - r.t);
+        if (s >= 0.0f) {
+            r.t += s;
+            return kDfHit;
+        }
+    }
+    if (t_exit >= r.b) return kDfMiss;
+    if (ex <= ey && ex <= ez) r.ci += r.qxf > 0.0f ? 1 : -1;
+    else if (ey <= ez) r.cj += r.qyf > 0.0f ? 1 : -1;
+    else r.ck += r.qzf > 0.0f ? 1 : -1;
+    if (r.ci < 0 || r.cj < 0 || r.ck < 0 || r.ci > nm2 || r.cj > nm2 || r.ck > nm2) return kDfMiss;
+    r.t = t_exit;
+    return kDfContinue;
+}
+
+// Upper bound on the iterations of one march: sphere steps are at least
+// h / L >= h / sqrt(3) long and cell steps enter a new cell along the ray.
+HYB_HD int df_max_steps(const Grid& g) { return 16 * g.n + 64; }
 
 // First t in [a, b] (clipped to the grid box) where the trilinear interpolant
 // of the samples is <= 0, or +inf.
 //
+// Every iteration fetches the 8 corners of one cell and then takes one of two
+// steps, so lanes of a wavefront in different phases still execute the same
+// instruction stream:
+//   sphere step  g > band (h, or 2h once walking): advance by a distance the
+//                interpolant cannot cross, max(g / L, g - two_e) (the second
+//                bound only for grids that certify 1-Lipschitz samples,
+//                two_e = 2 (sqrt(3)/2 h + q));
+//   cell step    near the surface: the ray's span inside the current cell; a
+//                cell whose 8 corners are all positive holds no root (the
+//                interpolant is a convex blend of them), otherwise the exact
+//                first root of the cell's cubic; then the next cell in DDA order.
 // The ray's position in cell units, X(t) = (o - lo)/h + t d/h, is formed in
 // FP64 (MI355X runs FP64 FMA at half the FP32 rate) so the in-cell fraction
-// X - floor(X) keeps full FP32 precision even tens of cells from the origin;
-// the per-cell cubic and its root are FP32.
+// keeps full FP32 precision tens of cells from the origin.
 template <bool COUNT>
 HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz, float a,
                            float b, Counters& cnt) {
-    // clip to the grid box [lo, lo + (n-1) h]^3
-    const float ext = (float)(g.n - 1) * g.h;
-    {
-        const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
-        const float t0x = (g.lo_x - ox) * ix, t1x = (g.lo_x + ext - ox) * ix;
-        const float t0y = (g.lo_y - oy) * iy, t1y = (g.lo_y + ext - oy) * iy;
-        const float t0z = (g.lo_z - oz) * iz, t1z = (g.lo_z + ext - oz) * iz;
-        a = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), a));
-        b = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), b));
-        if (!(a <= b)) return __builtin_inff();
-    }
-    const double ih = g.inv_hd;
-    const double px = ((double)ox - (double)g.lo_x) * ih, py = ((double)oy - (double)g.lo_y) * ih,
-                 pz = ((double)oz - (double)g.lo_z) * ih;
-    const double qx = (double)dx * ih, qy = (double)dy * ih, qz = (double)dz * ih;
-    const double iqx = qx != 0.0 ? 1.0 / qx : 0.0, iqy = qy != 0.0 ? 1.0 / qy : 0.0, iqz = qz != 0.0 ? 1.0 / qz : 0.0;
-    const float qxf = (float)qx, qyf = (float)qy, qzf = (float)qz;
-    const int nm2 = g.n - 2;
-    const float band_in = 1.0f * g.h, band_out = 2.0f * g.h;
-    float t = a;
-    float f[8];
-    for (int guard = 0; guard < 16 * g.n + 64; ++guard) {
-        // sphere-tracing phase: the cell of X(t) by floor
-        double X = fma((double)t, qx, px), Y = fma((double)t, qy, py), Z = fma((double)t, qz, pz);
-        int ci = min(max((int)floor(X), 0), nm2);
-        int cj = min(max((int)floor(Y), 0), nm2);
-        int ck = min(max((int)floor(Z), 0), nm2);
-        corners(g, ci, cj, ck, f);
-        if (COUNT) cnt.df++;
-        float fx = (float)(X - ci), fy = (float)(Y - cj), fz = (float)(Z - ck);
-        float val = lerp_cell(f, fx, fy, fz);
-        if (val <= 0.0f) return t;
-        if (val > band_in) {
-            t = fmaf(val, g.inv_l, t);
-            if (t > b) return __builtin_inff();
-            continue;
-        }
-        // near the surface: walk cells in order, exact root of each cell's cubic
-        for (; guard < 16 * g.n + 64; ++guard) {
-            // exit face per axis; an axis the ray does not move along never exits
-            const float ex = qx != 0.0 ? (float)(((qx > 0.0 ? ci + 1 : ci) - px) * iqx) : __builtin_inff();
-            const float ey = qy != 0.0 ? (float)(((qy > 0.0 ? cj + 1 : cj) - py) * iqy) : __builtin_inff();
-            const float ez = qz != 0.0 ? (float)(((qz > 0.0 ? ck + 1 : ck) - pz) * iqz) : __builtin_inff();
-            const float t_exit = fminf(fminf(ex, ey), ez);
-            const float t_end = fminf(t_exit, b);
-            float k[4];
-            cell_cubic(f, fx, fy, fz, qxf, qyf, qzf, k);
-            const float s = cell_first_root(k, t_end - t);
-            if (s >= 0.0f) return t + s;
-            if (t_exit >= b) return __builtin_inff();
-            // step into the neighbour across the exit face
-            if (ex <= ey && ex <= ez) ci += qx > 0.0 ? 1 : -1;
-            else if (ey <= ez) cj += qy > 0.0 ? 1 : -1;
-            else ck += qz > 0.0 ? 1 : -1;
-            if (ci < 0 || cj < 0 || ck < 0 || ci > nm2 || cj > nm2 || ck > nm2) return __builtin_inff();
-            t = fmaxf(t, t_exit);
-            X = fma((double)t, qx, px);
-            Y = fma((double)t, qy, py);
-            Z = fma((double)t, qz, pz);
-            fx = (float)(X - ci);
-            fy = (float)(Y - cj);
-            fz = (float)(Z - ck);
-            corners(g, ci, cj, ck, f);
-            if (COUNT) cnt.df++;
-            val = lerp_cell(f, fx, fy, fz);
-            if (val > band_out) break;  // far enough again: back to sphere steps
-        }
+    DfRay r;
+    if (!df_init(g, ox, oy, oz, dx, dy, dz, a, b, r)) return __builtin_inff();
+    const int max_steps = df_max_steps(g);
+    for (int it = 0; it < max_steps; ++it) {
+        const int st = df_step<COUNT>(g, r, cnt);
+        if (st == kDfHit) return r.t;
+        if (st == kDfMiss) return __builtin_inff();
     }
     return __builtin_inff();
 }
@@ -401,6 +482,17 @@ inline float finish_lipschitz(float cell_max) { return fmaxf(cell_max, 1.0f) * (
 // Reciprocal step factor: g * inv_step(L) is a safe sphere-tracing step.
 inline float inv_step(float lipschitz) { return (1.0f / lipschitz) * (1.0f - 1e-6f); }
 
+// Step slack for grids whose samples are FP32 roundings of a 1-Lipschitz
+// function f (an exact distance field).  Then |f~ - f| <= E + q with
+// E = sqrt(3)/2 h (the largest blend of corner distances inside a cell) and q
+// the storage error, so f~ stays positive for a distance g - 2 (E + q) ahead.
+// q covers one FP32 rounding of any sample (|f| <= the grid diagonal) plus a
+// margin of 1e-4 h.
+inline float certified_slack(float h, int n) {
+    const float q = 1e-4f * h + 2.4e-7f * 1.7320508f * (float)(n - 1) * h;
+    return 2.0f * (0.8660254f * h * (1.0f + 1e-6f) + q);
+}
+
 // One ray of a query (the body of the trace kernels).
 template <int MODE, bool COUNT>
 HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
@@ -414,7 +506,7 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
     hit.u = 0.0f;
     hit.v = 0.0f;
     if (tmin <= a.tmax) {
-        const Grid g = {a.sdf, a.n_grid, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, 1.0 / (double)a.h};
+        const Grid g = {a.sdf, a.n_grid, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e, 1.0 / (double)a.h};
         if (MODE == kBvhOnly) {
             hit = bvh_closest<COUNT>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, a.tmax, stack, stride, cnt);
         } else if (MODE == kDfOnly) {

@@ -22,6 +22,7 @@ struct TraceArgs {
     const float* sdf;
     int32_t n_grid;
     float lo_x, lo_y, lo_z, h, inv_h, inv_l;
+    float two_e;  // certified-grid step slack (+inf: use g / L only)
     // query
     float tmax, tau;
     int64_t n;

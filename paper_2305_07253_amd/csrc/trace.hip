@@ -20,8 +20,8 @@ __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a) {
 
 template <int MODE, bool COUNT>
 static hipError_t launch(const TraceArgs& a, hipStream_t stream) {
-    const int64_t blocks = (a.n + kBlock - 1) / kBlock;
     const size_t lds = MODE == kDfOnly ? 0 : sizeof(int) * kLdsDepth * kBlock;
+    const int64_t blocks = (a.n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL((k_trace<MODE, COUNT>), dim3((unsigned)blocks), dim3(kBlock), lds, stream, a);
     return hipGetLastError();
 }

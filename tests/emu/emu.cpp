@@ -5,7 +5,8 @@
 //   emu <input.bin> <output.bin>
 //
 // input:  int64 hdr[8] = {what, n_rays, n_verts, n_tris, N, has_tmin, mode, 0}
-//         float par[8] = {tmax, tau, lo_x, lo_y, lo_z, h, exterior_solid, 0}
+//         float par[8] = {tmax, tau, lo_x, lo_y, lo_z, h, flag, 0}
+//         flag: exterior solid (what 1) / certified 1-Lipschitz samples (what 0)
 //         verts f32[3 n_verts], tris i32[3 n_tris], grid f32[N^3] (what 0, N > 0),
 //         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays] (has_tmin)
 // what 0 (trace): output t f32[n], prim i32[n], u f32[n], v f32[n], counts i32[3n]
@@ -93,6 +94,7 @@ int main(int argc, char** argv) {
     a.n_grid = (int)N;
     a.lo_x = par[2]; a.lo_y = par[3]; a.lo_z = par[4]; a.h = par[5]; a.inv_h = inv_h;
     a.inv_l = hyb::inv_step(L);
+    a.two_e = par[6] != 0.0f ? hyb::certified_slack(par[5], (int)N) : __builtin_inff();
     a.tmax = par[0];
     a.tau = par[1];
     a.n = n;

@@ -54,8 +54,9 @@ def _run(hdr, par, arrays, out_bytes):
         return data
 
 
-def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None):
-    """Returns (t, prim, u, v, counts) exactly as the kernels compute them."""
+def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, certified=False):
+    """Returns (t, prim, u, v, counts) exactly as the kernels compute them;
+    `certified` marks the grid samples as exact distances."""
     rays_soa = np.ascontiguousarray(rays_soa, dtype=np.float32)
     n = rays_soa.shape[1]
     N = 0 if grid is None else np.asarray(grid).shape[-1]
@@ -67,7 +68,7 @@ def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None):
     if tmin is not None:
         arrays.append(np.asarray(tmin, np.float32))
     hdr = [0, n, len(verts), len(tris), N, tmin is not None, mode, 0]
-    par = [tmax, tau, g4[0], g4[1], g4[2], g4[3], 0, 0]
+    par = [tmax, tau, g4[0], g4[1], g4[2], g4[3], 1.0 if certified else 0.0, 0]
     raw = _run(hdr, par, arrays, 4 * n * 7)
     t = raw[: 4 * n].view(np.float32)
     prim = raw[4 * n: 8 * n].view(np.int32)

@@ -59,9 +59,11 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.hyb_build_bvh(vp, -1, tp, 1, None, ctypes.byref(out)) == 1
     # bad grids for hyb_sdf_from_grid
     g = np.array([0, 0, 0, -1], np.float32)
-    assert lib.hyb_sdf_from_grid(P(1), 8, g.ctypes.data_as(P), 0, None, ctypes.byref(out)) == 1
+    assert lib.hyb_sdf_from_grid(P(1), 8, g.ctypes.data_as(P), 0, 0, None, ctypes.byref(out)) == 1
+    g[3] = 0.1
+    assert lib.hyb_sdf_from_grid(P(1), 8, g.ctypes.data_as(P), 8, 0, None, ctypes.byref(out)) == 1  # unknown flag
     g[3] = np.inf
-    assert lib.hyb_sdf_from_grid(P(1), 8, g.ctypes.data_as(P), 0, None, ctypes.byref(out)) == 1
+    assert lib.hyb_sdf_from_grid(P(1), 8, g.ctypes.data_as(P), 0, 0, None, ctypes.byref(out)) == 1
 
 
 def test_python_binding_validates(lib):

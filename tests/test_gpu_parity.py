@@ -39,19 +39,22 @@ def tiny_dev(hyb, tiny):
     sc = tiny["scene"]
     bvh = hyb.build_bvh(sc.verts, sc.tris)
     sdf = hyb.sdf_from_grid(to_dev(tiny["grid"].reshape(-1)), tiny["grid4"])
-    return dict(bvh=bvh, sdf=sdf, free=to_dev(tiny["free"].soa()), surf=to_dev(tiny["surf"].soa()))
+    # the oracle's grid is exact, so it may be certified (longer safe steps)
+    sdf_c = hyb.sdf_from_grid(to_dev(tiny["grid"].reshape(-1)), tiny["grid4"], lipschitz_samples=True)
+    return dict(bvh=bvh, sdf=sdf, sdf_c=sdf_c, free=to_dev(tiny["free"].soa()), surf=to_dev(tiny["surf"].soa()))
 
 
+@pytest.mark.parametrize("grid_kind", ["sdf", "sdf_c"])
 @pytest.mark.parametrize("which", ["free", "surf"])
 @pytest.mark.parametrize("tau", TAUS)
-def test_tiny_combined(hyb, orc, tiny, tiny_dev, which, tau):
+def test_tiny_combined(hyb, orc, tiny, tiny_dev, which, tau, grid_kind):
     sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
     s = tiny[which].soa()
-    got = host(hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], tiny_dev[which], 2.0, tau))
+    got = host(hyb.trace(tiny_dev["bvh"], tiny_dev[grid_kind], tiny_dev[which], 2.0, tau))
     ref = orc.query(sc.verts, sc.tris, grid, g4, s, 2.0, tau)
     m, c = orc.margin(sc.verts, sc.tris, grid, g4, s, 2.0, tau)
-    st = parity.check(got, ref, m, c, label="gpu tiny %s tau=%s" % (which, tau))
-    print("tiny", which, tau, st)
+    st = parity.check(got, ref, m, c, label="gpu tiny %s tau=%s %s" % (which, tau, grid_kind))
+    print("tiny", which, tau, grid_kind, st)
 
 
 @pytest.mark.parametrize("which", ["free", "surf"])

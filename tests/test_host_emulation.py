@@ -17,15 +17,17 @@ def emu():
     return runner
 
 
+@pytest.mark.parametrize("certified", [False, True])
 @pytest.mark.parametrize("which", ["free", "surf"])
 @pytest.mark.parametrize("tau", TAUS)
-def test_combined_matches_oracle(emu, orc, tiny, which, tau):
+def test_combined_matches_oracle(emu, orc, tiny, which, tau, certified):
+    """certified: the grid is exact, so the tracer may also step by g - 2E."""
     sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
     rays = tiny[which]
-    got = emu.trace(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, tau)
+    got = emu.trace(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, tau, certified=certified)
     ref = orc.query(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, tau)
     m, c = orc.margin(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, tau)
-    parity.check(got, ref, m, c, label="emu %s tau=%s" % (which, tau))
+    parity.check(got, ref, m, c, label="emu %s tau=%s certified=%s" % (which, tau, certified))
 
 
 @pytest.mark.parametrize("mode", [1, 2])
@@ -47,6 +49,15 @@ def test_limits_equal_pure_kernels(emu, tiny):
         b = emu.trace(sc.verts, sc.tris, grid, g4, s, 2.0, tau, mode=mode)
         for x, y in zip(a[:4], b[:4]):
             assert np.array_equal(x, y)
+
+
+def test_certified_steps_are_not_more(emu, tiny):
+    """The certified bound only ever lengthens steps."""
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    s = tiny["free"].soa()
+    a = emu.trace(sc.verts, sc.tris, grid, g4, s, 2.0, 0.0, mode=2)
+    b = emu.trace(sc.verts, sc.tris, grid, g4, s, 2.0, 0.0, mode=2, certified=True)
+    assert np.all(b[4][:, 2] <= a[4][:, 2] + 1)
 
 
 def test_early_exit_takes_no_df_steps(emu, tiny):
