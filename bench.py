@@ -50,6 +50,29 @@ def time_launches(fn, stream, reps, warmup):
     return start.elapsed_time(stop) / reps
 
 
+def source_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2305_07253_amd", "csrc", "*"))):
+        if f.endswith((".hpp", ".hip", ".cpp")):
+            h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(tau):
+    """HBM bytes per launch of the combined kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source at
+    this threshold; else None."""
+    f = os.path.join(ROOT, "profiles", "traffic_gi1080p.json")
+    if not os.path.exists(f):
+        return None
+    rec = json.load(open(f))
+    if rec.get("source_sha256") != source_sha256() or rec.get("threshold") != tau:
+        return None
+    return rec["read_bytes"] + rec["write_bytes"]
+
+
 def artefacts(t, prim, o, d, t_ref, prim_ref, o_ref, h):
     """Artefact rate against the triangle reference: hit/miss differs, or the
     hit points are more than one voxel apart; plus |dp|/h statistics over rays
@@ -223,7 +246,7 @@ def main():
                                    scene.n_tris, args.width, args.height, n, chosen["tau"]),
                    "rays": n, "triangles": scene.n_tris, "grid": 128, "tmax": TMAX, "threshold": chosen["tau"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(tau),
                      "bytes_per_ray": bytes_per_ray, "nodes_per_ray": c[0], "tris_per_ray": c[1],
                      "df_fetches_per_ray": c[2]},
         "cpu_baseline": cpu,

@@ -290,18 +290,22 @@ HYB_HD float refine_root(const float k[4], float a, float b, float tol) {
     return b;
 }
 
-// First s in (0, S] with g(s) <= 0 given g(0) > 0, or -1.
-// Exact rejection first: on [0, S] the cubic is a blend of its four Bernstein
-// coefficients, so if they are all positive g stays positive.  Otherwise g is
-// split into monotone pieces at the roots of g'; the first piece ending at or
-// below zero holds the first root.
-HYB_HD float cell_first_root(const float k[4], float S) {
-    if (!(S > 0.0f)) return -1.0f;
+// Exact rejection: on [0, S] the cubic is a blend of its four Bernstein
+// coefficients, so if they are all positive g stays positive.  True when the
+// span may hold a root.
+HYB_HD bool cubic_may_vanish(const float k[4], float S) {
+    if (!(S > 0.0f)) return false;
     const float k1 = k[1] * S, k2 = k[2] * S * S, k3 = k[3] * S * S * S;
     const float b1 = fmaf(k1, 1.0f / 3.0f, k[0]);
     const float b2 = fmaf(k2, 1.0f / 3.0f, fmaf(k1, 2.0f / 3.0f, k[0]));
     const float b3 = k[0] + k1 + k2 + k3;
-    if (b1 > 0.0f && b2 > 0.0f && b3 > 0.0f) return -1.0f;
+    return !(b1 > 0.0f && b2 > 0.0f && b3 > 0.0f);
+}
+
+// First s in (0, S] with g(s) <= 0 given g(0) > 0, or -1: g is split into
+// monotone pieces at the roots of g'; the first piece ending at or below zero
+// holds the first root.
+HYB_HD float cubic_first_root(const float k[4], float S) {
     float r0 = S, r1 = S;
     const float A = 3.0f * k[3], B = 2.0f * k[2], C = k[1];
     if (A != 0.0f) {
@@ -322,18 +326,21 @@ HYB_HD float cell_first_root(const float k[4], float S) {
         const float a = -C * approx_rcp(B);
         r0 = r1 = (a > 0.0f && a < S) ? a : S;
     }
-    // first piece whose end is at or below zero
     float lo = 0.0f, hi = S;
     if (cubic_at(k, r0) <= 0.0f) hi = r0;
     else if (r1 > r0 && cubic_at(k, r1) <= 0.0f) {
         lo = r0;
         hi = r1;
-    } else if (b3 <= 0.0f) {
+    } else if (cubic_at(k, S) <= 0.0f) {
         lo = r1;
     } else {
         return -1.0f;
     }
     return refine_root(k, lo, hi, 1e-6f * S);
+}
+
+HYB_HD float cell_first_root(const float k[4], float S) {
+    return cubic_may_vanish(k, S) ? cubic_first_root(k, S) : -1.0f;
 }
 
 // Marching state of one ray (see df_first_root).
@@ -345,9 +352,24 @@ struct DfRay {
     float t, b;         // current position and segment end
     int ci, cj, ck;     // current cell while walking
     bool walk;
+    // a cell span [t, t + span] whose cubic k may vanish, left for df_resolve
+    float k[4], span, t_exit;
+    int axis;           // exit face of that cell: 0, 1, 2
 };
 
-enum DfStatus : int { kDfContinue = 0, kDfHit = 1, kDfMiss = 2 };
+enum DfStatus : int { kDfContinue = 0, kDfHit = 1, kDfMiss = 2, kDfSolve = 3 };
+
+// Moves to the neighbouring cell across the exit face `axis` at t_exit.
+HYB_HD int df_advance(const Grid& g, DfRay& r, int axis, float t_exit) {
+    if (t_exit >= r.b) return kDfMiss;
+    if (axis == 0) r.ci += r.qxf > 0.0f ? 1 : -1;
+    else if (axis == 1) r.cj += r.qyf > 0.0f ? 1 : -1;
+    else r.ck += r.qzf > 0.0f ? 1 : -1;
+    const int nm2 = g.n - 2;
+    if (r.ci < 0 || r.cj < 0 || r.ck < 0 || r.ci > nm2 || r.cj > nm2 || r.ck > nm2) return kDfMiss;
+    r.t = t_exit;
+    return kDfContinue;
+}
 
 // Clips [a, b] to the grid box and prepares the marching state; false when the
 // segment misses the box.
@@ -371,9 +393,11 @@ HYB_HD bool df_init(const Grid& g, float ox, float oy, float oz, float dx, float
     r.qxf = (float)r.qx;
     r.qyf = (float)r.qy;
     r.qzf = (float)r.qz;
-    r.ix = r.qxf != 0.0f ? 1.0f / fabsf(r.qxf) : __builtin_inff();
-    r.iy = r.qyf != 0.0f ? 1.0f / fabsf(r.qyf) : __builtin_inff();
-    r.iz = r.qzf != 0.0f ? 1.0f / fabsf(r.qzf) : __builtin_inff();
+    // these only size the cell spans of the walk (a span a few ulps long or
+    // short moves a cell boundary by as much, on a continuous interpolant)
+    r.ix = r.qxf != 0.0f ? approx_rcp(fabsf(r.qxf)) : __builtin_inff();
+    r.iy = r.qyf != 0.0f ? approx_rcp(fabsf(r.qyf)) : __builtin_inff();
+    r.iz = r.qzf != 0.0f ? approx_rcp(fabsf(r.qzf)) : __builtin_inff();
     r.t = a;
     r.b = b;
     r.ci = r.cj = r.ck = 0;
@@ -382,7 +406,8 @@ HYB_HD bool df_init(const Grid& g, float ox, float oy, float oz, float dx, float
 }
 
 // One iteration of the march: fetch the 8 corners of one cell, then either a
-// sphere step or a cell step (see df_first_root).  On kDfHit the hit is r.t.
+// sphere step or a cell step (see df_first_root).  On kDfHit the hit is r.t;
+// kDfSolve leaves a cell span that may hold the first root for df_resolve.
 template <bool COUNT>
 HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     const int nm2 = g.n - 2;
@@ -409,24 +434,30 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     const float ey = (r.qyf > 0.0f ? 1.0f - fy : fy) * r.iy;
     const float ez = (r.qzf > 0.0f ? 1.0f - fz : fz) * r.iz;
     const float t_exit = r.t + fmaxf(fminf(fminf(ex, ey), ez), 0.0f);
+    const int axis = (ex <= ey && ex <= ez) ? 0 : (ey <= ez ? 1 : 2);
     const float fmin = fminf(fminf(fminf(f[0], f[1]), fminf(f[2], f[3])), fminf(fminf(f[4], f[5]), fminf(f[6], f[7])));
     if (fmin <= 0.0f) {
-        // some corner at or below zero: exact first root of this cell's cubic
-        float k[4];
-        cell_cubic(f, fx, fy, fz, r.qxf, r.qyf, r.qzf, k);
-        const float s = cell_first_root(k, fminf(t_exit, r.b) - r.t);
-        if (s >= 0.0f) {
-            r.t += s;
-            return kDfHit;
+        // some corner at or below zero: the cell's cubic along the ray
+        cell_cubic(f, fx, fy, fz, r.qxf, r.qyf, r.qzf, r.k);
+        r.span = fminf(t_exit, r.b) - r.t;
+        if (cubic_may_vanish(r.k, r.span)) {
+            r.t_exit = t_exit;
+            r.axis = axis;
+            return kDfSolve;
         }
     }
-    if (t_exit >= r.b) return kDfMiss;
-    if (ex <= ey && ex <= ez) r.ci += r.qxf > 0.0f ? 1 : -1;
-    else if (ey <= ez) r.cj += r.qyf > 0.0f ? 1 : -1;
-    else r.ck += r.qzf > 0.0f ? 1 : -1;
-    if (r.ci < 0 || r.cj < 0 || r.ck < 0 || r.ci > nm2 || r.cj > nm2 || r.ck > nm2) return kDfMiss;
-    r.t = t_exit;
-    return kDfContinue;
+    return df_advance(g, r, axis, t_exit);
+}
+
+// Finishes a kDfSolve: the exact first root of the cell's cubic, else on to
+// the next cell.
+HYB_HD int df_resolve(const Grid& g, DfRay& r) {
+    const float s = cubic_first_root(r.k, r.span);
+    if (s >= 0.0f) {
+        r.t += s;
+        return kDfHit;
+    }
+    return df_advance(g, r, r.axis, r.t_exit);
 }
 
 // Upper bound on the iterations of one march: sphere steps are at least
@@ -455,13 +486,17 @@ HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx
                            float b, Counters& cnt) {
     DfRay r;
     if (!df_init(g, ox, oy, oz, dx, dy, dz, a, b, r)) return __builtin_inff();
-    const int max_steps = df_max_steps(g);
-    for (int it = 0; it < max_steps; ++it) {
-        const int st = df_step<COUNT>(g, r, cnt);
+    // The cubic solve runs outside the marching loop: a lane leaves the loop
+    // at a cell that may hold its root and the wavefront solves all such lanes
+    // together (nearly every solve ends its ray).
+    int budget = df_max_steps(g);
+    for (;;) {
+        int st = kDfContinue;
+        for (; budget > 0 && st == kDfContinue; --budget) st = df_step<COUNT>(g, r, cnt);
+        if (st == kDfSolve) st = df_resolve(g, r);
         if (st == kDfHit) return r.t;
-        if (st == kDfMiss) return __builtin_inff();
+        if (st == kDfMiss || budget <= 0) return __builtin_inff();
     }
-    return __builtin_inff();
 }
 
 // Gradient bound of the trilinear interpolant inside one cell (corners f):
