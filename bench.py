@@ -150,9 +150,13 @@ def main():
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
+        s16 = hyb.build_sdf(bvh, 128, g128, fmt=hyb.SDF_F16)
+        s8 = hyb.build_sdf(bvh, 128, g128, fmt=hyb.SDF_I8_BRICK)
         for name, fn in (("combined", lambda: hyb.trace(bvh, sdf128, R, TMAX, tau, out=out)),
                          ("bvh_only", lambda: hyb.trace_bvh(bvh, R, TMAX, out=out)),
-                         ("df_only", lambda: hyb.trace_df(sdf128, R128, TMAX, out=out))):
+                         ("df_only", lambda: hyb.trace_df(sdf128, R128, TMAX, out=out)),
+                         ("combined_f16", lambda: hyb.trace(bvh, s16, R, TMAX, tau, out=out)),
+                         ("combined_i8", lambda: hyb.trace(bvh, s8, R, TMAX, tau, out=out))):
             ms = time_launches(fn, stream, args.steps, args.warmup)
             log("%s: %.4f ms per launch (%d rays)" % (name, ms, n))
         torch.cuda.synchronize()

@@ -48,11 +48,22 @@ typedef enum {
 typedef struct hyb_bvh_s* hyb_bvh; /* triangle BVH; library-owned device memory */
 typedef struct hyb_sdf_s* hyb_sdf; /* distance-field grid; library-owned device memory */
 
-/* Storage of the distance-field samples. */
+/* Storage of the distance-field samples (the paper motivates keeping the DF
+ * small, Sections 3 and 4).  The trace kernels interpolate the dequantized
+ * FP32 values; every node has exactly one value, so the interpolant stays
+ * continuous.  Triangle tests and t comparisons stay FP32.
+ *   HYB_SDF_F32       FP32 samples
+ *   HYB_SDF_F16       IEEE half, round to nearest even; value = (float)half
+ *   HYB_SDF_I8_BRICK  int8 per node plus one FP32 scale per 8^3 block of nodes
+ *                     (node (i,j,k) belongs to block (i/8, j/8, k/8)):
+ *                     scale = max |f| over the block / 127 (1 if that is 0),
+ *                     q = rint(f / scale) clamped to [-127, 127] (FP32 division,
+ *                     round half to even), value = q * scale (FP32).
+ * Compact formats do not use the certified-sample step bound. */
 typedef enum {
-    HYB_SDF_F32 = 0,     /* FP32 */
-    HYB_SDF_F16 = 1,     /* IEEE half */
-    HYB_SDF_I8_BRICK = 2 /* int8 with one FP32 scale per 8^3-cell brick */
+    HYB_SDF_F32 = 0,
+    HYB_SDF_F16 = 1,
+    HYB_SDF_I8_BRICK = 2
 } hyb_sdf_format;
 
 /* Rays: device SoA arrays of n floats each.  d must be unit length (the
@@ -116,9 +127,9 @@ hyb_status hyb_bvh_info(hyb_bvh bvh, int64_t* n_nodes, int64_t* n_tris, int32_t*
  *          h = largest extent / (n - 5).
  *   n      samples per axis, 8 <= n <= 1024.
  *   flags  HYB_SDF_EXTERIOR_SOLID or 0.
- *   fmt    storage format.
- * Errors: HYB_ERR_INVALID_ARG for a NULL bvh/out, bad n, h <= 0 or non-finite
- * grid4; HYB_ERR_OOM when the grid does not fit. */
+ *   fmt    storage format; the FP32 distances are converted after the build.
+ * Errors: HYB_ERR_INVALID_ARG for a NULL bvh/out, bad n, h <= 0, non-finite
+ * grid4, unknown flags or format; HYB_ERR_OOM when the grid does not fit. */
 hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t flags, hyb_sdf_format fmt,
                          void* stream, hyb_sdf* out);
 
@@ -126,7 +137,9 @@ hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t fl
  *   values  device, n^3 floats, x fastest: values[i + n (j + n k)]; 2 <= n <= 1024
  *   grid4   host, {lo_x, lo_y, lo_z, h}
  *   flags   0 or HYB_SDF_LIPSCHITZ_SAMPLES
- * The Lipschitz bound used for safe steps is recomputed from the values.
+ *   fmt     storage format the values are converted to
+ * The Lipschitz bound used for safe steps is recomputed from the stored
+ * (dequantized) values.
  * Errors: HYB_ERR_INVALID_ARG for NULL values/grid4/out, bad n, h <= 0,
  * non-finite grid4 or unknown flags. */
 hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4, uint32_t flags,

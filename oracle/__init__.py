@@ -66,6 +66,34 @@ def lib():
     return _lib
 
 
+FMT_F32, FMT_F16, FMT_I8 = 0, 1, 2
+SCALE_BLOCK = 8
+
+
+def quantize(grid, fmt):
+    """Compact storage of an FP32 grid (n,n,n) [k,j,i], as the library defines
+    it: returns (dequantized float32 grid, stored values, block scales or None).
+      F16: round to nearest even half.
+      I8:  per 8^3 block of nodes (node (i,j,k) -> block (i//8, j//8, k//8)),
+           scale = max|f| / 127 in FP32 (1 if 0); q = rint(f / scale) in FP32,
+           clamped to [-127, 127]; value = q * scale in FP32."""
+    g = np.ascontiguousarray(grid, dtype=np.float32)
+    if fmt == FMT_F32:
+        return g, g, None
+    if fmt == FMT_F16:
+        h = g.astype(np.float16)
+        return h.astype(np.float32), h, None
+    n = g.shape[-1]
+    nb = (n + SCALE_BLOCK - 1) // SCALE_BLOCK
+    pad = nb * SCALE_BLOCK - n
+    a = np.pad(np.abs(g), ((0, pad), (0, pad), (0, pad)))
+    m = a.reshape(nb, SCALE_BLOCK, nb, SCALE_BLOCK, nb, SCALE_BLOCK).max(axis=(1, 3, 5)).astype(np.float32)
+    scales = np.where(m > 0, m / np.float32(127.0), np.float32(1.0)).astype(np.float32)
+    s = np.repeat(np.repeat(np.repeat(scales, SCALE_BLOCK, 0), SCALE_BLOCK, 1), SCALE_BLOCK, 2)[:n, :n, :n]
+    q = np.clip(np.rint(g / s), -127, 127).astype(np.float32)
+    return (q * s).astype(np.float32), q.astype(np.int8), scales
+
+
 def threads() -> int:
     """OpenMP threads the oracle's loops run on."""
     return int(lib().oracle_threads())

@@ -24,8 +24,10 @@ struct hyb_bvh_s {
 
 struct hyb_sdf_s {
     int device = 0;
-    float* values = nullptr;  // n^3 FP32 samples, x fastest
-    int32_t n = 0;
+    float* values = nullptr;  // n^3 FP32 samples as the kernels see them (dequantized), x fastest
+    void* store = nullptr;    // F16 / I8 storage the kernels read (null for F32)
+    float* scales = nullptr;  // I8 block scales
+    int32_t n = 0, nb = 0;
     float grid4[4] = {0, 0, 0, 0};
     float lipschitz = 0.0f;
     bool certified = false;  // samples are FP32 roundings of a 1-Lipschitz function
@@ -77,6 +79,21 @@ hyb_status compute_lipschitz(hyb_sdf_s* s, hipStream_t stream) {
     return HYB_OK;
 }
 
+// Converts the FP32 samples in s->values to the handle's storage format; the
+// dequantized values replace s->values in place.
+hyb_status quantize(hyb_sdf_s* s, hipStream_t stream) {
+    if (s->fmt == HYB_SDF_F32) return HYB_OK;
+    const size_t count = static_cast<size_t>(s->n) * s->n * s->n;
+    s->nb = (s->n + hyb::kScaleBlock - 1) / hyb::kScaleBlock;
+    HYB_TRY(hipMalloc(&s->store, count * (s->fmt == HYB_SDF_F16 ? 2 : 1)));
+    if (s->fmt == HYB_SDF_I8_BRICK)
+        HYB_TRY(hipMalloc(&s->scales, sizeof(float) * static_cast<size_t>(s->nb) * s->nb * s->nb));
+    return from_hip(hyb::launch_quantize(s->fmt == HYB_SDF_F16 ? hyb::kF16 : hyb::kI8, s->values, s->n, s->store,
+                                         s->scales, s->values, stream));
+}
+
+bool valid_fmt(hyb_sdf_format f) { return f == HYB_SDF_F32 || f == HYB_SDF_F16 || f == HYB_SDF_I8_BRICK; }
+
 bool valid_grid4(const float* g) {
     return g && std::isfinite(g[0]) && std::isfinite(g[1]) && std::isfinite(g[2]) && std::isfinite(g[3]) &&
            g[3] > 0.0f;
@@ -99,7 +116,10 @@ void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s) {
         a.tris = b->tris;
     }
     if (s) {
-        a.sdf = s->values;
+        a.sdf = s->fmt == HYB_SDF_F32 ? static_cast<const void*>(s->values) : s->store;
+        a.scales = s->scales;
+        a.fmt = static_cast<int32_t>(s->fmt);
+        a.nb = s->nb;
         a.n_grid = s->n;
         a.lo_x = s->grid4[0];
         a.lo_y = s->grid4[1];
@@ -107,7 +127,7 @@ void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s) {
         a.h = s->grid4[3];
         a.inv_h = 1.0f / s->grid4[3];
         a.inv_l = hyb::inv_step(s->lipschitz);
-        a.two_e = s->certified ? hyb::certified_slack(s->grid4[3], s->n) : __builtin_inff();
+        a.two_e = (s->certified && s->fmt == HYB_SDF_F32) ? hyb::certified_slack(s->grid4[3], s->n) : __builtin_inff();
     }
 }
 
@@ -187,8 +207,7 @@ hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t fl
                          void* stream, hyb_sdf* out) {
     if (!out) return HYB_ERR_INVALID_ARG;
     *out = nullptr;
-    if (!bvh || n < 8 || n > 1024 || (flags & ~HYB_SDF_EXTERIOR_SOLID)) return HYB_ERR_INVALID_ARG;
-    if (fmt != HYB_SDF_F32) return HYB_ERR_UNSUPPORTED;
+    if (!bvh || n < 8 || n > 1024 || (flags & ~HYB_SDF_EXTERIOR_SOLID) || !valid_fmt(fmt)) return HYB_ERR_INVALID_ARG;
     if (!same_device(bvh->device)) return HYB_ERR_INVALID_ARG;
     float g4[4];
     if (grid4) {
@@ -224,6 +243,7 @@ hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t fl
         e = hyb::launch_sdf_build(a, st);
     }
     hyb_status rc = from_hip(e);
+    if (rc == HYB_OK) rc = quantize(s, st);
     if (rc == HYB_OK) rc = compute_lipschitz(s, st);
     if (rc != HYB_OK) {
         hyb_sdf_destroy(s);
@@ -237,9 +257,8 @@ hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4,
                              void* stream, hyb_sdf* out) {
     if (!out) return HYB_ERR_INVALID_ARG;
     *out = nullptr;
-    if (!values || n < 2 || n > 1024 || !valid_grid4(grid4) || (flags & ~HYB_SDF_LIPSCHITZ_SAMPLES))
+    if (!values || n < 2 || n > 1024 || !valid_grid4(grid4) || (flags & ~HYB_SDF_LIPSCHITZ_SAMPLES) || !valid_fmt(fmt))
         return HYB_ERR_INVALID_ARG;
-    if (fmt != HYB_SDF_F32) return HYB_ERR_UNSUPPORTED;
     hyb_sdf_s* s = new (std::nothrow) hyb_sdf_s;
     if (!s) return HYB_ERR_OOM;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -252,6 +271,7 @@ hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4,
     if (e == hipSuccess) e = hipMalloc(&s->values, bytes);
     if (e == hipSuccess) e = hipMemcpyAsync(s->values, values, bytes, hipMemcpyDeviceToDevice, st);
     hyb_status rc = from_hip(e);
+    if (rc == HYB_OK) rc = quantize(s, st);
     if (rc == HYB_OK) rc = compute_lipschitz(s, st);
     if (rc != HYB_OK) {
         hyb_sdf_destroy(s);
@@ -278,6 +298,8 @@ hyb_status hyb_sdf_read(hyb_sdf sdf, float* out, void* stream) {
 hyb_status hyb_sdf_destroy(hyb_sdf sdf) {
     if (!sdf) return HYB_ERR_INVALID_ARG;
     if (sdf->values) (void)hipFree(sdf->values);
+    if (sdf->store) (void)hipFree(sdf->store);
+    if (sdf->scales) (void)hipFree(sdf->scales);
     delete sdf;
     return HYB_OK;
 }

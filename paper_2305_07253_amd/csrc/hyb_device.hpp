@@ -202,27 +202,43 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
 // distance field
 // ---------------------------------------------------------------------------
 
+enum SdfFormat : int { kF32 = 0, kF16 = 1, kI8 = 2 };
+constexpr int kScaleBlock = 8;  // I8: one scale per 8^3 block of nodes
+
 struct Grid {
-    const float* __restrict__ v;  // n^3 samples, x fastest
-    int n;
+    const void* __restrict__ v;        // n^3 samples, x fastest (float, _Float16 or int8_t)
+    const float* __restrict__ scales;  // I8: per node block (node (i,j,k) -> block (i/8, j/8, k/8))
+    int n, nb;                         // samples per axis, scale blocks per axis
     float lo_x, lo_y, lo_z, h, inv_h;
     float inv_l;    // 1 / Lipschitz bound of the interpolant (slightly reduced)
     float two_e;    // 2 x (interpolation error bound + storage error), +inf if uncertified
     double inv_hd;  // 1 / h in FP64
 };
 
+// The 8 corner samples of cell (i, j, k), dequantized to FP32:
+// f[dx + 2 dy + 4 dz] = sample(i + dx, j + dy, k + dz).
+template <int FMT>
 HYB_HD void corners(const Grid& g, int i, int j, int k, float f[8]) {
     const int64_t n = g.n;
-    const float* p = g.v + (int64_t)i + n * ((int64_t)j + n * (int64_t)k);
-    const int64_t sy = n, sz = n * n;
-    f[0] = p[0];
-    f[1] = p[1];
-    f[2] = p[sy];
-    f[3] = p[sy + 1];
-    f[4] = p[sz];
-    f[5] = p[sz + 1];
-    f[6] = p[sz + sy];
-    f[7] = p[sz + sy + 1];
+    const int64_t base = (int64_t)i + n * ((int64_t)j + n * (int64_t)k);
+    const int64_t off[8] = {0, 1, n, n + 1, n * n, n * n + 1, n * n + n, n * n + n + 1};
+    if constexpr (FMT == kF32) {
+        const float* p = static_cast<const float*>(g.v) + base;
+        for (int c = 0; c < 8; ++c) f[c] = p[off[c]];
+    } else if constexpr (FMT == kF16) {
+        const _Float16* p = static_cast<const _Float16*>(g.v) + base;
+        for (int c = 0; c < 8; ++c) f[c] = (float)p[off[c]];
+    } else {
+        const int8_t* p = static_cast<const int8_t*>(g.v) + base;
+        const int bi0 = i / kScaleBlock, bi1 = (i + 1) / kScaleBlock;
+        const int bj0 = j / kScaleBlock, bj1 = (j + 1) / kScaleBlock;
+        const int bk0 = k / kScaleBlock, bk1 = (k + 1) / kScaleBlock;
+        const int nb = g.nb;
+        for (int c = 0; c < 8; ++c) {
+            const int bi = (c & 1) ? bi1 : bi0, bj = (c & 2) ? bj1 : bj0, bk = (c & 4) ? bk1 : bk0;
+            f[c] = (float)p[off[c]] * g.scales[bi + nb * (bj + nb * bk)];
+        }
+    }
 }
 
 HYB_HD float lerp_cell(const float f[8], float x, float y, float z) {
@@ -408,7 +424,7 @@ HYB_HD bool df_init(const Grid& g, float ox, float oy, float oz, float dx, float
 // One iteration of the march: fetch the 8 corners of one cell, then either a
 // sphere step or a cell step (see df_first_root).  On kDfHit the hit is r.t;
 // kDfSolve leaves a cell span that may hold the first root for df_resolve.
-template <bool COUNT>
+template <int FMT, bool COUNT>
 HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     const int nm2 = g.n - 2;
     const double X = fma((double)r.t, r.qx, r.px), Y = fma((double)r.t, r.qy, r.py), Z = fma((double)r.t, r.qz, r.pz);
@@ -419,7 +435,7 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     }
     const float fx = (float)(X - r.ci), fy = (float)(Y - r.cj), fz = (float)(Z - r.ck);
     float f[8];
-    corners(g, r.ci, r.cj, r.ck, f);
+    corners<FMT>(g, r.ci, r.cj, r.ck, f);
     if (COUNT) cnt.df++;
     const float val = lerp_cell(f, fx, fy, fz);
     if (val <= 0.0f) return kDfHit;
@@ -481,7 +497,7 @@ HYB_HD int df_max_steps(const Grid& g) { return 16 * g.n + 64; }
 // The ray's position in cell units, X(t) = (o - lo)/h + t d/h, is formed in
 // FP64 (MI355X runs FP64 FMA at half the FP32 rate) so the in-cell fraction
 // keeps full FP32 precision tens of cells from the origin.
-template <bool COUNT>
+template <int FMT, bool COUNT>
 HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz, float a,
                            float b, Counters& cnt) {
     DfRay r;
@@ -492,7 +508,7 @@ HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx
     int budget = df_max_steps(g);
     for (;;) {
         int st = kDfContinue;
-        for (; budget > 0 && st == kDfContinue; --budget) st = df_step<COUNT>(g, r, cnt);
+        for (; budget > 0 && st == kDfContinue; --budget) st = df_step<FMT, COUNT>(g, r, cnt);
         if (st == kDfSolve) st = df_resolve(g, r);
         if (st == kDfHit) return r.t;
         if (st == kDfMiss || budget <= 0) return __builtin_inff();
@@ -529,7 +545,7 @@ inline float certified_slack(float h, int n) {
 }
 
 // One ray of a query (the body of the trace kernels).
-template <int MODE, bool COUNT>
+template <int MODE, int FMT, bool COUNT>
 HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
     const float ox = a.ox[i], oy = a.oy[i], oz = a.oz[i];
     const float dx = a.dx[i], dy = a.dy[i], dz = a.dz[i];
@@ -541,11 +557,12 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
     hit.u = 0.0f;
     hit.v = 0.0f;
     if (tmin <= a.tmax) {
-        const Grid g = {a.sdf, a.n_grid, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e, 1.0 / (double)a.h};
+        const Grid g = {a.sdf, a.scales, a.n_grid, a.nb, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e,
+                        1.0 / (double)a.h};
         if (MODE == kBvhOnly) {
             hit = bvh_closest<COUNT>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, a.tmax, stack, stride, cnt);
         } else if (MODE == kDfOnly) {
-            const float t = df_first_root<COUNT>(g, ox, oy, oz, dx, dy, dz, tmin, a.tmax, cnt);
+            const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, tmin, a.tmax, cnt);
             if (t < __builtin_inff()) {
                 hit.t = t;
                 hit.prim = -2;
@@ -557,7 +574,7 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
             const float t1 = fminf(fmaf(a.tau, a.h, tmin), a.tmax);
             if (t1 > tmin) hit = bvh_closest<COUNT>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt);
             if (hit.prim < 0 && (t1 < a.tmax || a.tau == 0.0f)) {
-                const float t = df_first_root<COUNT>(g, ox, oy, oz, dx, dy, dz, t1, a.tmax, cnt);
+                const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, a.tmax, cnt);
                 if (t < __builtin_inff()) {
                     hit.t = t;
                     hit.prim = -2;

@@ -19,8 +19,10 @@ struct TraceArgs {
     // scene
     const float4* nodes;
     const float4* tris;
-    const float* sdf;
-    int32_t n_grid;
+    const void* sdf;      // samples in the grid's storage format
+    const float* scales;  // I8 block scales or null
+    int32_t fmt;          // SdfFormat
+    int32_t n_grid, nb;
     float lo_x, lo_y, lo_z, h, inv_h, inv_l;
     float two_e;  // certified-grid step slack (+inf: use g / L only)
     // query
@@ -29,6 +31,14 @@ struct TraceArgs {
 };
 
 hipError_t launch_trace(int mode, bool counters, const TraceArgs& a, hipStream_t stream);
+
+// Storage conversion of an n^3 FP32 grid (x fastest).
+//   F16: out16[i] = round-to-nearest-even half of in[i]
+//   I8:  scales[b] = max |in| over the nodes of 8^3 block b / 127 (1 if that is 0),
+//        out8[i] = rint(in[i] / scale of its block) clamped to [-127, 127]
+// deq receives the dequantized FP32 values (what the trace kernels see).
+hipError_t launch_quantize(int fmt, const float* in, int32_t n, void* out, float* scales, float* deq,
+                           hipStream_t stream);
 
 struct SdfBuildArgs {
     const float4* nodes;

@@ -40,7 +40,60 @@ __global__ __launch_bounds__(256) void k_lipschitz(const float* __restrict__ g, 
     if (threadIdx.x == 0) block_max[blockIdx.x] = red[0];
 }
 
+// I8 block scales: one thread per 8^3 block of nodes, max |f| / 127.
+__global__ __launch_bounds__(256) void k_block_scales(const float* __restrict__ in, int32_t n, int32_t nb,
+                                                      float* __restrict__ scales) {
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= (int64_t)nb * nb * nb) return;
+    const int bi = (int)(b % nb), bj = (int)((b / nb) % nb), bk = (int)(b / ((int64_t)nb * nb));
+    float m = 0.0f;
+    for (int k = bk * kScaleBlock; k < min(n, (bk + 1) * kScaleBlock); ++k)
+        for (int j = bj * kScaleBlock; j < min(n, (bj + 1) * kScaleBlock); ++j)
+            for (int i = bi * kScaleBlock; i < min(n, (bi + 1) * kScaleBlock); ++i)
+                m = fmaxf(m, fabsf(in[i + (int64_t)n * (j + (int64_t)n * k)]));
+    scales[b] = m > 0.0f ? m / 127.0f : 1.0f;
+}
+
+// Per-node conversion to F16 or I8 and the dequantized FP32 value.
+template <int FMT>
+__global__ __launch_bounds__(256) void k_quantize(const float* __restrict__ in, int32_t n, int32_t nb, void* out,
+                                                  const float* __restrict__ scales, float* __restrict__ deq) {
+    const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nn = (int64_t)n;
+    if (id >= nn * nn * nn) return;
+    const float f = in[id];
+    if constexpr (FMT == kF16) {
+        const _Float16 q = (_Float16)f;
+        static_cast<_Float16*>(out)[id] = q;
+        deq[id] = (float)q;
+    } else {
+        const int i = (int)(id % nn), j = (int)((id / nn) % nn), k = (int)(id / (nn * nn));
+        const float s = scales[i / kScaleBlock + nb * (j / kScaleBlock + nb * (k / kScaleBlock))];
+        const float q = fminf(fmaxf(rintf(f / s), -127.0f), 127.0f);
+        static_cast<int8_t*>(out)[id] = (int8_t)q;
+        deq[id] = q * s;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_quantize(int fmt, const float* in, int32_t n, void* out, float* scales, float* deq,
+                           hipStream_t stream) {
+    const int64_t total = (int64_t)n * n * n;
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    const int32_t nb = (n + kScaleBlock - 1) / kScaleBlock;
+    if (fmt == kF16) {
+        hipLaunchKernelGGL(k_quantize<kF16>, dim3(blocks), dim3(256), 0, stream, in, n, nb, out, scales, deq);
+    } else if (fmt == kI8) {
+        const int64_t nbb = (int64_t)nb * nb * nb;
+        hipLaunchKernelGGL(k_block_scales, dim3((unsigned)((nbb + 255) / 256)), dim3(256), 0, stream, in, n, nb,
+                           scales);
+        hipLaunchKernelGGL(k_quantize<kI8>, dim3(blocks), dim3(256), 0, stream, in, n, nb, out, scales, deq);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_sdf_build(const SdfBuildArgs& a, hipStream_t stream) {
     const int64_t total = (int64_t)a.n_grid * a.n_grid * a.n_grid;

@@ -10,31 +10,42 @@
 
 namespace hyb {
 
-template <int MODE, bool COUNT>
+template <int MODE, int FMT, bool COUNT>
 __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a) {
     extern __shared__ int s_stack[];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.n) return;
-    trace_ray<MODE, COUNT>(a, i, s_stack + threadIdx.x, kBlock);
+    trace_ray<MODE, FMT, COUNT>(a, i, s_stack + threadIdx.x, kBlock);
 }
 
-template <int MODE, bool COUNT>
+template <int MODE, int FMT, bool COUNT>
 static hipError_t launch(const TraceArgs& a, hipStream_t stream) {
     const size_t lds = MODE == kDfOnly ? 0 : sizeof(int) * kLdsDepth * kBlock;
     const int64_t blocks = (a.n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL((k_trace<MODE, COUNT>), dim3((unsigned)blocks), dim3(kBlock), lds, stream, a);
+    hipLaunchKernelGGL((k_trace<MODE, FMT, COUNT>), dim3((unsigned)blocks), dim3(kBlock), lds, stream, a);
     return hipGetLastError();
+}
+
+template <int MODE, bool COUNT>
+static hipError_t launch_fmt(const TraceArgs& a, hipStream_t stream) {
+    if constexpr (MODE == kBvhOnly) return launch<MODE, kF32, COUNT>(a, stream);
+    switch (a.fmt) {
+        case kF32: return launch<MODE, kF32, COUNT>(a, stream);
+        case kF16: return launch<MODE, kF16, COUNT>(a, stream);
+        case kI8: return launch<MODE, kI8, COUNT>(a, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_trace(int mode, bool counters, const TraceArgs& a, hipStream_t stream) {
     if (a.n <= 0) return hipSuccess;
     switch (mode * 2 + (counters ? 1 : 0)) {
-        case 0: return launch<kCombined, false>(a, stream);
-        case 1: return launch<kCombined, true>(a, stream);
-        case 2: return launch<kBvhOnly, false>(a, stream);
-        case 3: return launch<kBvhOnly, true>(a, stream);
-        case 4: return launch<kDfOnly, false>(a, stream);
-        case 5: return launch<kDfOnly, true>(a, stream);
+        case 0: return launch_fmt<kCombined, false>(a, stream);
+        case 1: return launch_fmt<kCombined, true>(a, stream);
+        case 2: return launch_fmt<kBvhOnly, false>(a, stream);
+        case 3: return launch_fmt<kBvhOnly, true>(a, stream);
+        case 4: return launch_fmt<kDfOnly, false>(a, stream);
+        case 5: return launch_fmt<kDfOnly, true>(a, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -4,10 +4,12 @@
 //
 //   emu <input.bin> <output.bin>
 //
-// input:  int64 hdr[8] = {what, n_rays, n_verts, n_tris, N, has_tmin, mode, 0}
+// input:  int64 hdr[8] = {what, n_rays, n_verts, n_tris, N, has_tmin, mode, fmt}
 //         float par[8] = {tmax, tau, lo_x, lo_y, lo_z, h, flag, 0}
 //         flag: exterior solid (what 1) / certified 1-Lipschitz samples (what 0)
-//         verts f32[3 n_verts], tris i32[3 n_tris], grid f32[N^3] (what 0, N > 0),
+//         verts f32[3 n_verts], tris i32[3 n_tris],
+//         grid (what 0, N > 0): f32[N^3] dequantized values, then the stored
+//           values (f16 or i8 [N^3]) and f32 block scales [nb^3] for fmt 1/2,
 //         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays] (has_tmin)
 // what 0 (trace): output t f32[n], prim i32[n], u f32[n], v f32[n], counts i32[3n]
 // what 1 (sdf):   output f32[N^3] signed distances of the grid nodes
@@ -36,9 +38,14 @@ int main(int argc, char** argv) {
     auto hdr = rd<long long>(f, 8);
     auto par = rd<float>(f, 8);
     const long long what = hdr[0], n = hdr[1], nv = hdr[2], nt = hdr[3], N = hdr[4], has_tmin = hdr[5], mode = hdr[6];
+    const int fmt = (int)hdr[7];
+    const long long nb = (N + hyb::kScaleBlock - 1) / hyb::kScaleBlock;
     auto verts = rd<float>(f, 3 * nv);
     auto tris = rd<int32_t>(f, 3 * nt);
     std::vector<float> grid = what == 0 && N > 0 ? rd<float>(f, N * N * N) : std::vector<float>();
+    std::vector<_Float16> g16 = what == 0 && N > 0 && fmt == 1 ? rd<_Float16>(f, N * N * N) : std::vector<_Float16>();
+    std::vector<int8_t> g8 = what == 0 && N > 0 && fmt == 2 ? rd<int8_t>(f, N * N * N) : std::vector<int8_t>();
+    std::vector<float> scales = what == 0 && N > 0 && fmt == 2 ? rd<float>(f, nb * nb * nb) : std::vector<float>();
     auto rays = rd<float>(f, 6 * n);
     auto tmin = has_tmin ? rd<float>(f, n) : std::vector<float>();
     fclose(f);
@@ -90,19 +97,32 @@ int main(int argc, char** argv) {
     a.t = t.data(); a.prim = prim.data(); a.u = u.data(); a.v = v.data(); a.counts = counts.data();
     a.nodes = nodes.data();
     a.tris = tri4.data();
-    a.sdf = grid.empty() ? nullptr : grid.data();
+    a.sdf = grid.empty() ? nullptr
+            : (fmt == 1 ? static_cast<const void*>(g16.data())
+                        : (fmt == 2 ? static_cast<const void*>(g8.data()) : static_cast<const void*>(grid.data())));
+    a.scales = scales.empty() ? nullptr : scales.data();
+    a.fmt = fmt;
+    a.nb = (int)nb;
     a.n_grid = (int)N;
     a.lo_x = par[2]; a.lo_y = par[3]; a.lo_z = par[4]; a.h = par[5]; a.inv_h = inv_h;
     a.inv_l = hyb::inv_step(L);
-    a.two_e = par[6] != 0.0f ? hyb::certified_slack(par[5], (int)N) : __builtin_inff();
+    a.two_e = (par[6] != 0.0f && fmt == 0) ? hyb::certified_slack(par[5], (int)N) : __builtin_inff();
     a.tmax = par[0];
     a.tau = par[1];
     a.n = n;
     std::vector<int> stack(hyb::kLdsDepth);
     for (long long i = 0; i < n; ++i) {
-        if (mode == 0) hyb::trace_ray<hyb::kCombined, true>(a, i, stack.data(), 1);
-        else if (mode == 1) hyb::trace_ray<hyb::kBvhOnly, true>(a, i, stack.data(), 1);
-        else hyb::trace_ray<hyb::kDfOnly, true>(a, i, stack.data(), 1);
+        if (mode == 1) hyb::trace_ray<hyb::kBvhOnly, hyb::kF32, true>(a, i, stack.data(), 1);
+        else if (fmt == 1) {
+            if (mode == 0) hyb::trace_ray<hyb::kCombined, hyb::kF16, true>(a, i, stack.data(), 1);
+            else hyb::trace_ray<hyb::kDfOnly, hyb::kF16, true>(a, i, stack.data(), 1);
+        } else if (fmt == 2) {
+            if (mode == 0) hyb::trace_ray<hyb::kCombined, hyb::kI8, true>(a, i, stack.data(), 1);
+            else hyb::trace_ray<hyb::kDfOnly, hyb::kI8, true>(a, i, stack.data(), 1);
+        } else {
+            if (mode == 0) hyb::trace_ray<hyb::kCombined, hyb::kF32, true>(a, i, stack.data(), 1);
+            else hyb::trace_ray<hyb::kDfOnly, hyb::kF32, true>(a, i, stack.data(), 1);
+        }
     }
     fwrite(t.data(), 4, n, o);
     fwrite(prim.data(), 4, n, o);

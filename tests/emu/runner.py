@@ -54,20 +54,29 @@ def _run(hdr, par, arrays, out_bytes):
         return data
 
 
-def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, certified=False):
+def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, certified=False, fmt=0):
     """Returns (t, prim, u, v, counts) exactly as the kernels compute them;
-    `certified` marks the grid samples as exact distances."""
+    `certified` marks the grid samples as exact distances; `fmt` stores the
+    FP32 grid as F16 (1) or I8 with block scales (2), quantized by the
+    oracle's definition of the formats."""
     rays_soa = np.ascontiguousarray(rays_soa, dtype=np.float32)
     n = rays_soa.shape[1]
     N = 0 if grid is None else np.asarray(grid).shape[-1]
     g4 = np.zeros(4, np.float32) if grid4 is None else np.asarray(grid4, np.float32)
     arrays = [np.asarray(verts, np.float32), np.asarray(tris, np.int32)]
     if N:
-        arrays.append(np.asarray(grid, np.float32))
+        import oracle
+        deq, stored, scales = oracle.quantize(np.asarray(grid, np.float32), fmt)
+        arrays.append(deq)
+        if fmt == 1:
+            arrays.append(stored.astype(np.float16))
+        elif fmt == 2:
+            arrays.append(stored.astype(np.int8))
+            arrays.append(scales.astype(np.float32))
     arrays.append(rays_soa)
     if tmin is not None:
         arrays.append(np.asarray(tmin, np.float32))
-    hdr = [0, n, len(verts), len(tris), N, tmin is not None, mode, 0]
+    hdr = [0, n, len(verts), len(tris), N, tmin is not None, mode, fmt]
     par = [tmax, tau, g4[0], g4[1], g4[2], g4[3], 1.0 if certified else 0.0, 0]
     raw = _run(hdr, par, arrays, 4 * n * 7)
     t = raw[: 4 * n].view(np.float32)

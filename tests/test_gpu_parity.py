@@ -202,3 +202,58 @@ def test_gi_full_launch_sampled_parity(hyb, orc, gi, tau):
     m, c = orc.margin(sc.verts, sc.tris, grid, g4, sub.soa(), 0.5, tau)
     st = parity.check(got, ref, m, c, label="gi tau=%s" % tau)
     print("gi", tau, st)
+
+
+# ---------------------------------------------------------------------------
+# compact distance-field storage (F16, int8 with block scales)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_formats_quantize_and_trace(hyb, orc, tiny, tiny_dev, fmt):
+    """The library's conversion equals the oracle's definition bit for bit;
+    traces interpolate exactly those values."""
+    sc, g4 = tiny["scene"], tiny["grid4"]
+    sdf = hyb.sdf_from_grid(to_dev(tiny["grid"].reshape(-1)), g4, fmt=fmt)
+    deq, _, _ = orc.quantize(tiny["grid"], fmt)
+    got_grid = hyb.sdf_read(sdf).cpu().numpy()
+    assert np.array_equal(got_grid, deq)
+    assert abs(sdf.lipschitz - orc.lipschitz(deq, np.float64(g4[3]))) <= 1e-5
+    for which in ("free", "surf"):
+        for tau in (0.0, 1.0, np.inf):
+            got = host(hyb.trace(tiny_dev["bvh"], sdf, tiny_dev[which], 2.0, tau))
+            ref = orc.query(sc.verts, sc.tris, deq, g4, tiny[which].soa(), 2.0, tau)
+            m, c = orc.margin(sc.verts, sc.tris, deq, g4, tiny[which].soa(), 2.0, tau)
+            parity.check(got, ref, m, c, label="fmt %d %s tau %s" % (fmt, which, tau))
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_formats_build_sdf(hyb, orc, tiny, fmt):
+    """hyb_build_sdf with a compact format: the GPU's FP32 distances (within
+    one ulp of the oracle's) converted by the format's rule; at most one
+    quantisation step from the oracle's converted grid."""
+    sc, g4 = tiny["scene"], tiny["grid4"]
+    bvh = hyb.build_bvh(sc.verts, sc.tris)
+    got = hyb.sdf_read(hyb.build_sdf(bvh, 32, g4, fmt=fmt)).cpu().numpy().astype(np.float64)
+    deq, _, scales = orc.quantize(tiny["grid"], fmt)
+    if fmt == 1:
+        step = np.maximum(np.spacing(np.abs(deq).astype(np.float16)).astype(np.float64), 2.0 ** -24)
+    else:
+        step = np.repeat(np.repeat(np.repeat(scales, 8, 0), 8, 1), 8, 2)[:32, :32, :32].astype(np.float64)
+    assert np.all(np.abs(got - deq) <= step * (1 + 1e-6))
+    assert (got == deq).mean() > 0.999
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_gi_formats_full_launch(hyb, orc, gi, fmt):
+    """All 2,073,600 GI rays through an F16 / I8 copy of the oracle's 128^3
+    grid; 4,050 sampled rays against the oracle on the same dequantized grid."""
+    sc, g4 = gi["scene"], gi["g4"]
+    deq, _, _ = orc.quantize(gi["oracle_grid"], fmt)
+    sdf = hyb.sdf_from_grid(to_dev(gi["oracle_grid"].reshape(-1)), g4, fmt=fmt)
+    sub = gi["rays"].subset(gi["sample"])
+    for tau in (0.0, 1.0):
+        out = hyb.trace(gi["bvh"], sdf, gi["dev"], 0.5, tau)
+        got = [x.cpu().numpy()[gi["sample"]] for x in out]
+        ref = orc.query(sc.verts, sc.tris, deq, g4, sub.soa(), 0.5, tau)
+        m, c = orc.margin(sc.verts, sc.tris, deq, g4, sub.soa(), 0.5, tau)
+        parity.check(got, ref, m, c, label="gi fmt %d tau %s" % (fmt, tau))

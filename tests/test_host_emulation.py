@@ -30,6 +30,20 @@ def test_combined_matches_oracle(emu, orc, tiny, which, tau, certified):
     parity.check(got, ref, m, c, label="emu %s tau=%s certified=%s" % (which, tau, certified))
 
 
+@pytest.mark.parametrize("fmt", [1, 2])
+@pytest.mark.parametrize("tau", [0.0, 1.0, 4.0])
+def test_compact_formats_match_oracle(emu, orc, tiny, fmt, tau):
+    """F16 and I8 grids: the kernels interpolate the dequantized values, which
+    the oracle computes by the same definition."""
+    sc, g4 = tiny["scene"], tiny["grid4"]
+    deq, _, _ = orc.quantize(tiny["grid"], fmt)
+    for rays in (tiny["free"], tiny["surf"]):
+        got = emu.trace(sc.verts, sc.tris, tiny["grid"], g4, rays.soa(), 2.0, tau, fmt=fmt)
+        ref = orc.query(sc.verts, sc.tris, deq, g4, rays.soa(), 2.0, tau)
+        m, c = orc.margin(sc.verts, sc.tris, deq, g4, rays.soa(), 2.0, tau)
+        parity.check(got, ref, m, c, label="emu fmt %d tau %s" % (fmt, tau))
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_pure_modes_match_oracle(emu, orc, tiny, mode):
     sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]

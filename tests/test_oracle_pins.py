@@ -492,3 +492,50 @@ def test_o6_finite_differences(orc, tiny):
         tm = orc.df_hit(gm.reshape(grid.shape), g4, s, 0.0, 2.0)
         fd = (tp.sum() - tm.sum()) / (2 * delta)
         assert abs(fd - grad[j]) <= 1e-5 * max(1.0, abs(grad[j])), (j, fd, grad[j])
+
+
+# ---------------------------------------------------------------------------
+# compact storage formats
+# ---------------------------------------------------------------------------
+
+def test_quantize_f16_error_bound(orc, tiny):
+    g = tiny["grid"]
+    deq, stored, _ = orc.quantize(g, orc.FMT_F16)
+    assert stored.dtype == np.float16
+    # round to nearest: within half an ulp of half precision (2^-11 relative, normal range)
+    normal = np.abs(g) >= 2.0 ** -14
+    rel = np.abs(deq[normal].astype(np.float64) - g[normal]) / np.abs(g[normal])
+    assert rel.max() <= 2.0 ** -11
+    assert np.abs(deq[~normal].astype(np.float64) - g[~normal]).max() <= 2.0 ** -25
+
+
+def test_quantize_i8_blocks_and_bound(orc, tiny):
+    g = tiny["grid"]
+    n = g.shape[0]
+    deq, q, scales = orc.quantize(g, orc.FMT_I8)
+    nb = (n + 7) // 8
+    assert scales.shape == (nb, nb, nb) and q.dtype == np.int8
+    rng = np.random.default_rng(13)
+    for _ in range(200):
+        k, j, i = rng.integers(0, n, 3)
+        s = scales[k // 8, j // 8, i // 8]
+        # the node's own block scale; the largest |f| of the block maps to +-127
+        blk = g[k // 8 * 8:k // 8 * 8 + 8, j // 8 * 8:j // 8 * 8 + 8, i // 8 * 8:i // 8 * 8 + 8]
+        assert s == np.float32(np.abs(blk).max()) / np.float32(127)
+        assert abs(float(deq[k, j, i]) - float(g[k, j, i])) <= 0.5 * s * (1 + 1e-6) + 1e-9
+        assert deq[k, j, i] == np.float32(q[k, j, i]) * s
+    assert np.abs(q).max() == 127
+
+
+def test_quantized_interpolant_stays_continuous(orc, tiny):
+    """Each node has one stored value, so the interpolant agrees across a face
+    shared by two cells of different scale blocks."""
+    deq, _, _ = orc.quantize(tiny["grid"], orc.FMT_I8)
+    g4 = tiny["grid4"]
+    h = np.float64(g4[3])
+    for face in (8, 16, 24):  # node planes where scale blocks meet
+        x = g4[0] + face * h
+        for y, z in ((0.31, 0.52), (0.67, 0.44)):
+            a = orc.df_value(deq, g4, (x - 1e-12, y, z))
+            b = orc.df_value(deq, g4, (x + 1e-12, y, z))
+            assert abs(a - b) < 1e-9
