@@ -150,13 +150,17 @@ def main():
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
+        srays, stmax = W.shadow_rays(gb.p, gb.n, 22)
+        RS, TS = torch.from_numpy(srays.soa()).to(dev), torch.from_numpy(stmax).to(dev)
         s16 = hyb.build_sdf(bvh, 128, g128, fmt=hyb.SDF_F16)
         s8 = hyb.build_sdf(bvh, 128, g128, fmt=hyb.SDF_I8_BRICK)
         for name, fn in (("combined", lambda: hyb.trace(bvh, sdf128, R, TMAX, tau, out=out)),
                          ("bvh_only", lambda: hyb.trace_bvh(bvh, R, TMAX, out=out)),
                          ("df_only", lambda: hyb.trace_df(sdf128, R128, TMAX, out=out)),
                          ("combined_f16", lambda: hyb.trace(bvh, s16, R, TMAX, tau, out=out)),
-                         ("combined_i8", lambda: hyb.trace(bvh, s8, R, TMAX, tau, out=out))):
+                         ("combined_i8", lambda: hyb.trace(bvh, s8, R, TMAX, tau, out=out)),
+                         ("shadow", lambda: hyb.trace_shadow(bvh, sdf128, RS, 10.0, 1.0, 1.0, tmax_ray=TS, out=out)),
+                         ("shadow_bvh", lambda: hyb.trace_bvh(bvh, RS, 10.0, tmax_ray=TS, out=out))):
             ms = time_launches(fn, stream, args.steps, args.warmup)
             log("%s: %.4f ms per launch (%d rays)" % (name, ms, n))
         torch.cuda.synchronize()

@@ -67,12 +67,15 @@ typedef enum {
 } hyb_sdf_format;
 
 /* Rays: device SoA arrays of n floats each.  d must be unit length (the
- * distance-field steps assume it).  tmin may be NULL (tmin = 0 for every ray);
- * a ray with tmin > tmax is reported as a miss. */
+ * distance-field steps assume it).  tmin may be NULL (tmin = 0 for every ray).
+ * tmax may be NULL (every ray uses the call's scalar tmax); otherwise ray i
+ * ends at min(tmax[i], scalar tmax) (shadow rays end at their light sample).
+ * A ray with tmin > tmax is reported as a miss. */
 typedef struct {
     const float *ox, *oy, *oz;
     const float *dx, *dy, *dz;
     const float* tmin;
+    const float* tmax;
 } hyb_rays;
 
 /* Hits: caller-allocated device SoA arrays of n entries.
@@ -169,11 +172,27 @@ hyb_status hyb_trace_bvh(hyb_bvh bvh, const hyb_rays* rays, int64_t n, float tma
 /* Pure distance-field tracing on [tmin, tmax] (the paper's DF-only baseline). */
 hyb_status hyb_trace_df(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits, void* stream);
 
+/* The paper's shadow-ray query (Section 3, GI & shadow rays; Section 2,
+ * any-hit processed out of order): three sub-intervals
+ *     [tmin, t1]  triangles     t1 = min(fl32(tmin + threshold_start * h), tmax)
+ *     [t1, t2]    distance field t2 = max(fl32(tmax - threshold_end * h), t1)
+ *     [t2, tmax]  triangles
+ * where any intersection suffices: the distance-field part runs first, then
+ * the triangle parts, each stopping at the first intersection found.
+ * Output per ray: prim -1 unoccluded (t = +inf); -2 occluded by the distance
+ * field (t = its first root in [t1, t2]); >= 0 occluded by that triangle (t =
+ * one of its intersections in a triangle part; which occluder is reported when
+ * there are several is unspecified).  Both thresholds 0: pure DF; +inf: pure
+ * triangles.  Errors as hyb_trace. */
+hyb_status hyb_trace_shadow(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax,
+                            float threshold_start, float threshold_end, hyb_hits* hits, void* stream);
+
 /* Work counters of one query, for measurement: the same trace as hyb_trace
  * (mode 0), hyb_trace_bvh (mode 1) or hyb_trace_df (mode 2), writing hits and,
  * per ray, counts[3 i + 0] BVH nodes visited, counts[3 i + 1] triangles
  * tested, counts[3 i + 2] distance-field sample fetches (8 corners each).
- *   counts  device, 3 n int32.  bvh may be NULL for mode 2, sdf for mode 1. */
+ *   counts  device, 3 n int32.  bvh may be NULL for mode 2, sdf for mode 1.
+ * mode 3 is hyb_trace_shadow with threshold_start = threshold_end = threshold. */
 hyb_status hyb_trace_counters(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax,
                               float threshold, int32_t mode, hyb_hits* hits, int32_t* counts, void* stream);
 

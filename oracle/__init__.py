@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-MODE_COMBINED, MODE_BVH, MODE_DF = 0, 1, 2
+MODE_COMBINED, MODE_BVH, MODE_DF, MODE_SHADOW = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:
@@ -56,8 +56,8 @@ def lib():
         L.oracle_lipschitz.argtypes = [P, i32, f64]
         L.oracle_lipschitz.restype = f64
         L.oracle_sphere_trace.argtypes = [P, i32, P, f64, P, i64, P, P, f64, i64, P, P]
-        L.oracle_query.argtypes = [P, P, i64, P, i32, P, P, i64, P, f32, f32, i32, P, P, P, P]
-        L.oracle_margin.argtypes = [P, P, i64, P, i32, P, P, i64, P, f32, f32, i32, P, P]
+        L.oracle_query.argtypes = [P, P, i64, P, i32, P, P, i64, P, P, f32, f32, f32, i32, P, P, P, P]
+        L.oracle_margin.argtypes = [P, P, i64, P, i32, P, P, i64, P, P, f32, f32, f32, i32, P, P]
         L.oracle_df_grad.argtypes = [P, i32, P, P, i64, P, P, P, P, P]
         L.oracle_sdf_points.argtypes = [P, P, i64, P, P, P, i32, P, i64, P]
         L.oracle_df_values.argtypes = [P, i32, P, P, i64, P]
@@ -210,31 +210,37 @@ def sphere_trace(grid, grid4, L, rays_soa, a, b, eps, max_steps=1_000_000):
     return out, st
 
 
-def query(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=MODE_COMBINED, tmin=None):
-    """O-4.  Returns (t, prim, u, v); prim -1 miss, -2 distance-field hit."""
+def query(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=MODE_COMBINED, tmin=None, tmax_ray=None,
+          tau_end=0.0):
+    """O-4 (mode 0), triangles only (1), DF only (2), shadow any-hit (3).
+    Returns (t, prim, u, v); prim -1 miss, -2 distance-field hit."""
     v, t = _f32(verts), _i32(tris)
     g = None if grid is None else _grid(grid)
     N = 0 if g is None else g.shape[-1]
     r, n = _rays(rays_soa)
     tm = None if tmin is None else _f32(tmin)
+    tx = None if tmax_ray is None else _f32(tmax_ray)
     to, uo, vo = np.empty(n), np.empty(n), np.empty(n)
     po = np.empty(n, dtype=np.int32)
     lib().oracle_query(_p(v), _p(t), t.shape[0], _p(g), N, None if grid4 is None else _p(_f32(grid4)),
-                       _p(r), n, _p(tm), np.float32(tmax), np.float32(tau), mode,
+                       _p(r), n, _p(tm), _p(tx), np.float32(tmax), np.float32(tau), np.float32(tau_end), mode,
                        _p(to), _p(po), _p(uo), _p(vo))
     return to, po, uo, vo
 
 
-def margin(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=MODE_COMBINED, tmin=None):
+def margin(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=MODE_COMBINED, tmin=None, tmax_ray=None,
+           tau_end=0.0):
     """Per-ray (margin, conditioning) of query(): see oracle.c."""
     v, t = _f32(verts), _i32(tris)
     g = None if grid is None else _grid(grid)
     N = 0 if g is None else g.shape[-1]
     r, n = _rays(rays_soa)
     tm = None if tmin is None else _f32(tmin)
+    tx = None if tmax_ray is None else _f32(tmax_ray)
     mo, co = np.empty(n), np.empty(n)
     lib().oracle_margin(_p(v), _p(t), t.shape[0], _p(g), N, None if grid4 is None else _p(_f32(grid4)),
-                        _p(r), n, _p(tm), np.float32(tmax), np.float32(tau), mode, _p(mo), _p(co))
+                        _p(r), n, _p(tm), _p(tx), np.float32(tmax), np.float32(tau), np.float32(tau_end), mode,
+                        _p(mo), _p(co))
     return mo, co
 
 

@@ -554,18 +554,30 @@ static double split_point(float tmin, float tmax, float tau, float h) {
     return (double)(t1 < tmax ? t1 : tmax);
 }
 
+/* Second split point of the shadow query: t2 = max(fl32(tmax - tau_end h), t1). */
+static double split_end(float tmax, float tau_end, float h, double t1) {
+    float t2 = fmaf(-tau_end, h, tmax);
+    return (double)t2 > t1 ? (double)t2 : t1;
+}
+
 /* mode 0: combined (BVH on [tmin,t1] first, DF on [t1,tmax] only after a miss)
- * mode 1: triangles only on [tmin,tmax];  mode 2: distance field only on [tmin,tmax].
+ * mode 1: triangles only on [tmin,tmax];  mode 2: distance field only on [tmin,tmax]
+ * mode 3: shadow query, any hit: triangles on [tmin,t1] and [t2,tmax], DF on
+ *         [t1,t2]; reported: the DF's first root if it has one, else the
+ *         closest triangle of the first part, else of the last part.
+ * Ray i ends at min(tmax_ray[i], tmax) when tmax_ray is given.
  * prim: >= 0 triangle, -2 distance-field hit, -1 miss (t = +inf). */
 void oracle_query(const float* verts, const int32_t* tris, int64_t ntri,
                   const double* grid, int N, const float* grid4,
-                  const float* rays, int64_t n, const float* tmin, float tmax, float tau, int mode,
+                  const float* rays, int64_t n, const float* tmin, const float* tmax_ray, float tmax_all,
+                  float tau, float tau_end, int mode,
                   double* t_out, int32_t* prim_out, double* u_out, double* v_out) {
     grid_t G = {grid, N, mk(grid4 ? grid4[0] : 0, grid4 ? grid4[1] : 0, grid4 ? grid4[2] : 0), grid4 ? grid4[3] : 1.0};
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i) {
         vec o = ray_o(rays, n, i), d = ray_d(rays, n, i);
         float t0 = tmin ? tmin[i] : 0.0f;
+        float tmax = tmax_ray ? fminf(tmax_ray[i], tmax_all) : tmax_all;
         double t, u, v;
         int32_t prim;
         t_out[i] = INFINITY; prim_out[i] = -1; u_out[i] = 0.0; v_out[i] = 0.0;
@@ -581,6 +593,22 @@ void oracle_query(const float* verts, const int32_t* tris, int64_t ntri,
             continue;
         }
         double t1 = split_point(t0, tmax, tau, (float)G.h);
+        if (mode == 3) {
+            double t2 = split_end(tmax, tau_end, (float)G.h, t1);
+            if (t2 > t1 || (tau == 0.0f && tau_end == 0.0f)) {
+                t = df_first_root(&G, o, d, t1, t2);
+                if (t < INFINITY) { t_out[i] = t; prim_out[i] = -2; continue; }
+            }
+            if (t1 > t0) {
+                closest_one(verts, tris, ntri, o, d, t0, t1, &t, &prim, &u, &v);
+                if (prim >= 0) { t_out[i] = t; prim_out[i] = prim; u_out[i] = u; v_out[i] = v; continue; }
+            }
+            if ((double)tmax > t2) {
+                closest_one(verts, tris, ntri, o, d, t2, tmax, &t, &prim, &u, &v);
+                if (prim >= 0) { t_out[i] = t; prim_out[i] = prim; u_out[i] = u; v_out[i] = v; }
+            }
+            continue;
+        }
         if (t1 > t0) {
             closest_one(verts, tris, ntri, o, d, t0, t1, &t, &prim, &u, &v);
             if (prim >= 0) { t_out[i] = t; prim_out[i] = prim; u_out[i] = u; v_out[i] = v; continue; }
@@ -755,13 +783,14 @@ static void df_margin(const grid_t* G, vec o, vec d, double a, double b, double*
 /* Per-ray margin and conditioning of a query (mode as in oracle_query). */
 void oracle_margin(const float* verts, const int32_t* tris, int64_t ntri,
                    const double* grid, int N, const float* grid4,
-                   const float* rays, int64_t n, const float* tmin, float tmax, float tau, int mode,
-                   double* margin_out, double* cond_out) {
+                   const float* rays, int64_t n, const float* tmin, const float* tmax_ray, float tmax_all,
+                   float tau, float tau_end, int mode, double* margin_out, double* cond_out) {
     grid_t G = {grid, N, mk(grid4 ? grid4[0] : 0, grid4 ? grid4[1] : 0, grid4 ? grid4[2] : 0), grid4 ? grid4[3] : 1.0};
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < n; ++i) {
         vec o = ray_o(rays, n, i), d = ray_d(rays, n, i);
         float t0 = tmin ? tmin[i] : 0.0f;
+        float tmax = tmax_ray ? fminf(tmax_ray[i], tmax_all) : tmax_all;
         double m = INFINITY, cnd = 1.0, mt, ct, tw, md, cd, td;
         int32_t w;
         if (!(t0 <= tmax)) { margin_out[i] = m; cond_out[i] = cnd; continue; }
@@ -769,6 +798,21 @@ void oracle_margin(const float* verts, const int32_t* tris, int64_t ntri,
             tri_margin(verts, tris, ntri, o, d, t0, tmax, &m, &cnd, &w, &tw);
         } else if (mode == 2) {
             df_margin(&G, o, d, t0, tmax, &m, &cnd, &td);
+        } else if (mode == 3) {
+            /* any hit: the DF part decides alone when it has a root; otherwise
+             * both triangle parts take part in the decision */
+            double t1 = split_point(t0, tmax, tau, (float)G.h);
+            double t2 = split_end(tmax, tau_end, (float)G.h, t1);
+            int decided = 0;
+            if (t2 > t1 || (tau == 0.0f && tau_end == 0.0f)) {
+                df_margin(&G, o, d, t1, t2, &md, &cd, &td);
+                m = md; cnd = cd;
+                if (td < INFINITY) decided = 1;
+            }
+            if (!decided) {
+                if (t1 > t0) { tri_margin(verts, tris, ntri, o, d, t0, t1, &mt, &ct, &w, &tw); m = fmin(m, mt); cnd = ct; }
+                if ((double)tmax > t2) { tri_margin(verts, tris, ntri, o, d, t2, tmax, &mt, &ct, &w, &tw); m = fmin(m, mt); }
+            }
         } else {
             double t1 = split_point(t0, tmax, tau, (float)G.h);
             int done = 0;

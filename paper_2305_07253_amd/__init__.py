@@ -30,7 +30,7 @@ HYB_DF_HIT = -2
 EXTERIOR_SOLID = 1
 LIPSCHITZ_SAMPLES = 2
 SDF_F32, SDF_F16, SDF_I8_BRICK = 0, 1, 2
-MODE_COMBINED, MODE_BVH, MODE_DF = 0, 1, 2
+MODE_COMBINED, MODE_BVH, MODE_DF, MODE_SHADOW = 0, 1, 2, 3
 
 _STATUS = {0: "HYB_OK", 1: "HYB_ERR_INVALID_ARG", 2: "HYB_ERR_OOM", 3: "HYB_ERR_HIP", 4: "HYB_ERR_UNSUPPORTED"}
 
@@ -42,7 +42,7 @@ class HybError(RuntimeError):
 
 
 class _Rays(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in ("ox", "oy", "oz", "dx", "dy", "dz", "tmin")]
+    _fields_ = [(n, ctypes.c_void_p) for n in ("ox", "oy", "oz", "dx", "dy", "dz", "tmin", "tmax")]
 
 
 class _Hits(ctypes.Structure):
@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
             "hyb_trace_bvh": [P, P, i64, f32, P, P],
             "hyb_trace_df": [P, P, i64, f32, P, P],
             "hyb_trace_counters": [P, P, P, i64, f32, f32, i32, P, P, P],
+            "hyb_trace_shadow": [P, P, P, i64, f32, f32, f32, P, P],
             "hyb_bvh_destroy": [P],
             "hyb_sdf_destroy": [P],
         }
@@ -203,18 +204,19 @@ def sdf_read(sdf: Sdf, stream=None):
     return out
 
 
-def _rays_struct(rays, tmin):
+def _rays_struct(rays, tmin, tmax_ray=None):
     torch = _torch()
     if not (rays.is_cuda and rays.dtype == torch.float32 and rays.dim() == 2 and rays.shape[0] == 6
             and rays.is_contiguous()):
         raise ValueError("rays must be a contiguous (6, n) float32 CUDA tensor")
     n = rays.shape[1]
     base, step = rays.data_ptr(), 4 * n
-    r = _Rays(*[base + k * step for k in range(6)], None)
-    if tmin is not None:
-        if not (tmin.is_cuda and tmin.dtype == torch.float32 and tmin.numel() == n and tmin.is_contiguous()):
-            raise ValueError("tmin must be a contiguous float32 CUDA tensor of n entries")
-        r.tmin = tmin.data_ptr()
+    r = _Rays(*[base + k * step for k in range(6)], None, None)
+    for name, x in (("tmin", tmin), ("tmax", tmax_ray)):
+        if x is not None:
+            if not (x.is_cuda and x.dtype == torch.float32 and x.numel() == n and x.is_contiguous()):
+                raise ValueError("%s must be a contiguous float32 CUDA tensor of n entries" % name)
+            setattr(r, name, x.data_ptr())
     return r, n
 
 
@@ -240,11 +242,12 @@ def _query_args(tmax, threshold):
         raise ValueError("threshold must be >= 0")
 
 
-def trace(bvh: Bvh, sdf: Sdf, rays, tmax: float, threshold: float, tmin=None, out=None, stream=None):
+def trace(bvh: Bvh, sdf: Sdf, rays, tmax: float, threshold: float, tmin=None, out=None, stream=None, tmax_ray=None):
     """Combined first-hit query: triangles on [tmin, t1], distance field on
-    [t1, tmax], t1 = min(tmin + threshold*h, tmax).  Returns (t, prim, u, v)."""
+    [t1, tmax], t1 = min(tmin + threshold*h, tmax).  Returns (t, prim, u, v).
+    tmax_ray: optional per-ray end (min with tmax)."""
     _query_args(tmax, threshold)
-    r, n = _rays_struct(rays, tmin)
+    r, n = _rays_struct(rays, tmin, tmax_ray)
     out = alloc_hits(n) if out is None else out
     h = _hits_struct(out, n)
     _check("hyb_trace", lib().hyb_trace(bvh.handle, sdf.handle, ctypes.byref(r), n, tmax, threshold,
@@ -252,10 +255,10 @@ def trace(bvh: Bvh, sdf: Sdf, rays, tmax: float, threshold: float, tmin=None, ou
     return out
 
 
-def trace_bvh(bvh: Bvh, rays, tmax: float, tmin=None, out=None, stream=None):
+def trace_bvh(bvh: Bvh, rays, tmax: float, tmin=None, out=None, stream=None, tmax_ray=None):
     """Pure triangle tracing on [tmin, tmax]."""
     _query_args(tmax, None)
-    r, n = _rays_struct(rays, tmin)
+    r, n = _rays_struct(rays, tmin, tmax_ray)
     out = alloc_hits(n) if out is None else out
     h = _hits_struct(out, n)
     _check("hyb_trace_bvh", lib().hyb_trace_bvh(bvh.handle, ctypes.byref(r), n, tmax, ctypes.byref(h),
@@ -263,10 +266,10 @@ def trace_bvh(bvh: Bvh, rays, tmax: float, tmin=None, out=None, stream=None):
     return out
 
 
-def trace_df(sdf: Sdf, rays, tmax: float, tmin=None, out=None, stream=None):
+def trace_df(sdf: Sdf, rays, tmax: float, tmin=None, out=None, stream=None, tmax_ray=None):
     """Pure distance-field tracing on [tmin, tmax]."""
     _query_args(tmax, None)
-    r, n = _rays_struct(rays, tmin)
+    r, n = _rays_struct(rays, tmin, tmax_ray)
     out = alloc_hits(n) if out is None else out
     h = _hits_struct(out, n)
     _check("hyb_trace_df", lib().hyb_trace_df(sdf.handle, ctypes.byref(r), n, tmax, ctypes.byref(h),
@@ -274,13 +277,29 @@ def trace_df(sdf: Sdf, rays, tmax: float, tmin=None, out=None, stream=None):
     return out
 
 
+def trace_shadow(bvh: Bvh, sdf: Sdf, rays, tmax: float, threshold_start: float, threshold_end: float, tmin=None,
+                 tmax_ray=None, out=None, stream=None):
+    """Any-hit shadow query: triangles on [tmin, t1] and [t2, tmax], the
+    distance field on [t1, t2] (traced first).  prim -1 unoccluded, -2 DF
+    occluder, >= 0 a triangle occluder."""
+    _query_args(tmax, threshold_start)
+    _query_args(tmax, threshold_end)
+    r, n = _rays_struct(rays, tmin, tmax_ray)
+    out = alloc_hits(n) if out is None else out
+    h = _hits_struct(out, n)
+    _check("hyb_trace_shadow", lib().hyb_trace_shadow(bvh.handle, sdf.handle, ctypes.byref(r), n, tmax,
+                                                      threshold_start, threshold_end, ctypes.byref(h),
+                                                      _stream(stream)))
+    return out
+
+
 def trace_counters(bvh, sdf, rays, tmax: float, threshold: float, mode: int = MODE_COMBINED, tmin=None,
-                   stream=None):
+                   stream=None, tmax_ray=None):
     """The same query with per-ray work counters: returns (t, prim, u, v) and
     an int32 (n, 3) tensor of [BVH nodes, triangles tested, DF sample fetches]."""
     torch = _torch()
     _query_args(tmax, threshold)
-    r, n = _rays_struct(rays, tmin)
+    r, n = _rays_struct(rays, tmin, tmax_ray)
     out = alloc_hits(n)
     h = _hits_struct(out, n)
     counts = torch.zeros((n, 3), dtype=torch.int32, device="cuda")

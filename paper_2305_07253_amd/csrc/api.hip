@@ -99,11 +99,14 @@ bool valid_grid4(const float* g) {
            g[3] > 0.0f;
 }
 
-void fill_trace_args(hyb::TraceArgs& a, const hyb_rays* rays, hyb_hits* hits, int64_t n, float tmax, float tau) {
+void fill_trace_args(hyb::TraceArgs& a, const hyb_rays* rays, hyb_hits* hits, int64_t n, float tmax, float tau,
+                     float tau_end = 0.0f) {
     std::memset(&a, 0, sizeof(a));
     a.ox = rays->ox; a.oy = rays->oy; a.oz = rays->oz;
     a.dx = rays->dx; a.dy = rays->dy; a.dz = rays->dz;
     a.tmin = rays->tmin;
+    a.tmax_ray = rays->tmax;
+    a.tau_end = tau_end;
     a.t = hits->t; a.prim = hits->prim; a.u = hits->u; a.v = hits->v;
     a.tmax = tmax;
     a.tau = tau;
@@ -338,16 +341,31 @@ hyb_status hyb_trace_df(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax
     return from_hip(hyb::launch_trace(hyb::kDfOnly, false, a, static_cast<hipStream_t>(stream)));
 }
 
+hyb_status hyb_trace_shadow(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax,
+                            float threshold_start, float threshold_end, hyb_hits* hits, void* stream) {
+    if (!bvh || !sdf || std::isnan(threshold_start) || threshold_start < 0.0f || std::isnan(threshold_end) ||
+        threshold_end < 0.0f)
+        return HYB_ERR_INVALID_ARG;
+    hyb_status rc = check_query(rays, n, tmax, hits);
+    if (rc != HYB_OK || n == 0) return rc;
+    if (!same_device(bvh->device) || !same_device(sdf->device)) return HYB_ERR_INVALID_ARG;
+    hyb::TraceArgs a;
+    fill_trace_args(a, rays, hits, n, tmax, threshold_start, threshold_end);
+    fill_scene(a, bvh, sdf);
+    return from_hip(hyb::launch_trace(hyb::kShadow, false, a, static_cast<hipStream_t>(stream)));
+}
+
 hyb_status hyb_trace_counters(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, float threshold,
                               int32_t mode, hyb_hits* hits, int32_t* counts, void* stream) {
-    if (mode < 0 || mode > 2 || std::isnan(threshold) || threshold < 0.0f) return HYB_ERR_INVALID_ARG;
+    if (mode < 0 || mode > 3 || std::isnan(threshold) || threshold < 0.0f) return HYB_ERR_INVALID_ARG;
     if ((mode != 2 && !bvh) || (mode != 1 && !sdf)) return HYB_ERR_INVALID_ARG;
     hyb_status rc = check_query(rays, n, tmax, hits);
     if (rc != HYB_OK || n == 0) return rc;
     if (!counts) return HYB_ERR_INVALID_ARG;
     if ((bvh && !same_device(bvh->device)) || (sdf && !same_device(sdf->device))) return HYB_ERR_INVALID_ARG;
     hyb::TraceArgs a;
-    fill_trace_args(a, rays, hits, n, tmax, mode == 1 ? __builtin_inff() : (mode == 2 ? 0.0f : threshold));
+    fill_trace_args(a, rays, hits, n, tmax, mode == 1 ? __builtin_inff() : (mode == 2 ? 0.0f : threshold),
+                    mode == 3 ? threshold : 0.0f);
     fill_scene(a, mode == 2 ? nullptr : bvh, mode == 1 ? nullptr : sdf);
     a.counts = counts;
     return from_hip(hyb::launch_trace(mode, true, a, static_cast<hipStream_t>(stream)));

@@ -132,10 +132,11 @@ struct Hit {
 };
 
 // Closest triangle hit on [seg_lo, seg_hi] (both inclusive).  Equal t goes to
-// the smallest original triangle id, independent of traversal order.
+// the smallest original triangle id, independent of traversal order.  With
+// ANY the traversal stops at the first intersection it finds (any-hit).
 // `stack` points at this lane's first LDS slot; consecutive entries are
 // `stride` ints apart (one slot per thread of the block, no bank conflicts).
-template <bool COUNT>
+template <bool COUNT, bool ANY = false>
 HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                            float ox, float oy, float oz, float dx, float dy, float dz,
                                            float seg_lo, float seg_hi, int* stack, int stride, Counters& cnt) {
@@ -187,6 +188,7 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
                         best.u = u;
                         best.v = v;
                     }
+                    if (ANY) return best;
                 }
             }
         }
@@ -550,31 +552,49 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
     const float ox = a.ox[i], oy = a.oy[i], oz = a.oz[i];
     const float dx = a.dx[i], dy = a.dy[i], dz = a.dz[i];
     const float tmin = a.tmin ? a.tmin[i] : 0.0f;
+    const float tmax = a.tmax_ray ? fminf(a.tmax_ray[i], a.tmax) : a.tmax;
     Counters cnt;
     Hit hit;
     hit.t = __builtin_inff();
     hit.prim = -1;
     hit.u = 0.0f;
     hit.v = 0.0f;
-    if (tmin <= a.tmax) {
+    if (tmin <= tmax) {
         const Grid g = {a.sdf, a.scales, a.n_grid, a.nb, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e,
                         1.0 / (double)a.h};
         if (MODE == kBvhOnly) {
-            hit = bvh_closest<COUNT>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, a.tmax, stack, stride, cnt);
+            hit = bvh_closest<COUNT>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, tmax, stack, stride, cnt);
         } else if (MODE == kDfOnly) {
-            const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, tmin, a.tmax, cnt);
+            const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, tmin, tmax, cnt);
             if (t < __builtin_inff()) {
                 hit.t = t;
                 hit.prim = -2;
             }
+        } else if (MODE == kShadow) {
+            // Section 3 shadow rays: triangles near both ends, the distance
+            // field in between; any intersection suffices, so the cheap DF part
+            // runs first (Section 2, out-of-order any-hit processing).
+            const float t1 = fminf(fmaf(a.tau, a.h, tmin), tmax);
+            const float t2 = fmaxf(fmaf(-a.tau_end, a.h, tmax), t1);
+            if (t2 > t1 || (a.tau == 0.0f && a.tau_end == 0.0f)) {
+                const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, t2, cnt);
+                if (t < __builtin_inff()) {
+                    hit.t = t;
+                    hit.prim = -2;
+                }
+            }
+            if (hit.prim == -1 && t1 > tmin)
+                hit = bvh_closest<COUNT, true>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt);
+            if (hit.prim == -1 && tmax > t2)
+                hit = bvh_closest<COUNT, true>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, t2, tmax, stack, stride, cnt);
         } else {
             // Eq. (2) with two sub-queries processed in order (first hit):
             // triangles on [tmin, t1]; the distance field on [t1, tmax] only
             // when the first sub-query found nothing.
-            const float t1 = fminf(fmaf(a.tau, a.h, tmin), a.tmax);
+            const float t1 = fminf(fmaf(a.tau, a.h, tmin), tmax);
             if (t1 > tmin) hit = bvh_closest<COUNT>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt);
-            if (hit.prim < 0 && (t1 < a.tmax || a.tau == 0.0f)) {
-                const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, a.tmax, cnt);
+            if (hit.prim < 0 && (t1 < tmax || a.tau == 0.0f)) {
+                const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, tmax, cnt);
                 if (t < __builtin_inff()) {
                     hit.t = t;
                     hit.prim = -2;

@@ -6,11 +6,11 @@
 
 namespace hyb {
 
-enum TraceMode : int { kCombined = 0, kBvhOnly = 1, kDfOnly = 2 };
+enum TraceMode : int { kCombined = 0, kBvhOnly = 1, kDfOnly = 2, kShadow = 3 };
 
 struct TraceArgs {
     // rays (device SoA)
-    const float *ox, *oy, *oz, *dx, *dy, *dz, *tmin;
+    const float *ox, *oy, *oz, *dx, *dy, *dz, *tmin, *tmax_ray;
     // hits (device SoA)
     float* t;
     int32_t* prim;
@@ -26,7 +26,7 @@ struct TraceArgs {
     float lo_x, lo_y, lo_z, h, inv_h, inv_l;
     float two_e;  // certified-grid step slack (+inf: use g / L only)
     // query
-    float tmax, tau;
+    float tmax, tau, tau_end;
     int64_t n;
 };
 

@@ -46,6 +46,8 @@ hipError_t launch_trace(int mode, bool counters, const TraceArgs& a, hipStream_t
         case 3: return launch_fmt<kBvhOnly, true>(a, stream);
         case 4: return launch_fmt<kDfOnly, false>(a, stream);
         case 5: return launch_fmt<kDfOnly, true>(a, stream);
+        case 6: return launch_fmt<kShadow, false>(a, stream);
+        case 7: return launch_fmt<kShadow, true>(a, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -548,6 +548,26 @@ def gbuffer_rays(gb: GBuffer, seed: int, eps: float = 1e-5, spp: int = 1) -> Ray
     return Rays((p + eps * n).astype(np.float32), _normalize32(d))
 
 
+LIGHT_CORNER = np.array([0.35, 0.97, 0.35])
+LIGHT_EDGES = (np.array([0.3, 0.0, 0.0]), np.array([0.0, 0.0, 0.3]))
+
+
+def shadow_rays(p: np.ndarray, n: np.ndarray, seed: int, eps: float = 1e-5):
+    """Shadow rays from surface points p (normals n) to uniform samples on a
+    0.3 x 0.3 area light just below the ceiling.  Returns (Rays, tmax) with
+    tmax = the float32 distance to the light sample (rays from points that face
+    away from the light are kept; they are simply occluded by their own
+    surface's neighbourhood or not)."""
+    rng = _rng(seed)
+    u = rng.random((len(p), 2))
+    q = LIGHT_CORNER + u[:, :1] * LIGHT_EDGES[0] + u[:, 1:] * LIGHT_EDGES[1]
+    o = p + eps * n
+    v = q - o
+    dist = np.linalg.norm(v, axis=1)
+    d = _normalize32(v / dist[:, None])
+    return Rays(o.astype(np.float32), d), dist.astype(np.float32)
+
+
 def rebias(rays: Rays, gb: GBuffer, eps: float, spp: int = 1) -> Rays:
     """Same directions as `rays`, origins moved to p + eps*n (the large normal
     bias a distance-field-only trace needs against self-intersection)."""

@@ -4,13 +4,14 @@
 //
 //   emu <input.bin> <output.bin>
 //
-// input:  int64 hdr[8] = {what, n_rays, n_verts, n_tris, N, has_tmin, mode, fmt}
-//         float par[8] = {tmax, tau, lo_x, lo_y, lo_z, h, flag, 0}
+// input:  int64 hdr[8] = {what, n_rays, n_verts, n_tris, N, ray_arrays, mode, fmt}
+//         ray_arrays: bit 0 per-ray tmin follows, bit 1 per-ray tmax follows
+//         float par[8] = {tmax, tau, lo_x, lo_y, lo_z, h, flag, tau_end}
 //         flag: exterior solid (what 1) / certified 1-Lipschitz samples (what 0)
 //         verts f32[3 n_verts], tris i32[3 n_tris],
 //         grid (what 0, N > 0): f32[N^3] dequantized values, then the stored
 //           values (f16 or i8 [N^3]) and f32 block scales [nb^3] for fmt 1/2,
-//         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays] (has_tmin)
+//         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays], tmax f32[n_rays]
 // what 0 (trace): output t f32[n], prim i32[n], u f32[n], v f32[n], counts i32[3n]
 // what 1 (sdf):   output f32[N^3] signed distances of the grid nodes
 #include <cstdio>
@@ -47,7 +48,8 @@ int main(int argc, char** argv) {
     std::vector<int8_t> g8 = what == 0 && N > 0 && fmt == 2 ? rd<int8_t>(f, N * N * N) : std::vector<int8_t>();
     std::vector<float> scales = what == 0 && N > 0 && fmt == 2 ? rd<float>(f, nb * nb * nb) : std::vector<float>();
     auto rays = rd<float>(f, 6 * n);
-    auto tmin = has_tmin ? rd<float>(f, n) : std::vector<float>();
+    auto tmin = (has_tmin & 1) ? rd<float>(f, n) : std::vector<float>();
+    auto tmaxr = (has_tmin & 2) ? rd<float>(f, n) : std::vector<float>();
     fclose(f);
 
     hyb::BvhHost bvh;
@@ -93,7 +95,9 @@ int main(int argc, char** argv) {
     hyb::TraceArgs a{};
     a.ox = rays.data(); a.oy = rays.data() + n; a.oz = rays.data() + 2 * n;
     a.dx = rays.data() + 3 * n; a.dy = rays.data() + 4 * n; a.dz = rays.data() + 5 * n;
-    a.tmin = has_tmin ? tmin.data() : nullptr;
+    a.tmin = (has_tmin & 1) ? tmin.data() : nullptr;
+    a.tmax_ray = (has_tmin & 2) ? tmaxr.data() : nullptr;
+    a.tau_end = par[7];
     a.t = t.data(); a.prim = prim.data(); a.u = u.data(); a.v = v.data(); a.counts = counts.data();
     a.nodes = nodes.data();
     a.tris = tri4.data();
@@ -113,6 +117,7 @@ int main(int argc, char** argv) {
     std::vector<int> stack(hyb::kLdsDepth);
     for (long long i = 0; i < n; ++i) {
         if (mode == 1) hyb::trace_ray<hyb::kBvhOnly, hyb::kF32, true>(a, i, stack.data(), 1);
+        else if (mode == 3) hyb::trace_ray<hyb::kShadow, hyb::kF32, true>(a, i, stack.data(), 1);
         else if (fmt == 1) {
             if (mode == 0) hyb::trace_ray<hyb::kCombined, hyb::kF16, true>(a, i, stack.data(), 1);
             else hyb::trace_ray<hyb::kDfOnly, hyb::kF16, true>(a, i, stack.data(), 1);

@@ -54,7 +54,8 @@ def _run(hdr, par, arrays, out_bytes):
         return data
 
 
-def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, certified=False, fmt=0):
+def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, certified=False, fmt=0, tmax_ray=None,
+          tau_end=0.0):
     """Returns (t, prim, u, v, counts) exactly as the kernels compute them;
     `certified` marks the grid samples as exact distances; `fmt` stores the
     FP32 grid as F16 (1) or I8 with block scales (2), quantized by the
@@ -76,8 +77,10 @@ def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, cert
     arrays.append(rays_soa)
     if tmin is not None:
         arrays.append(np.asarray(tmin, np.float32))
-    hdr = [0, n, len(verts), len(tris), N, tmin is not None, mode, fmt]
-    par = [tmax, tau, g4[0], g4[1], g4[2], g4[3], 1.0 if certified else 0.0, 0]
+    if tmax_ray is not None:
+        arrays.append(np.asarray(tmax_ray, np.float32))
+    hdr = [0, n, len(verts), len(tris), N, (tmin is not None) | (2 if tmax_ray is not None else 0), mode, fmt]
+    par = [tmax, tau, g4[0], g4[1], g4[2], g4[3], 1.0 if certified else 0.0, tau_end]
     raw = _run(hdr, par, arrays, 4 * n * 7)
     t = raw[: 4 * n].view(np.float32)
     prim = raw[4 * n: 8 * n].view(np.int32)

@@ -61,3 +61,39 @@ def check(got, ref, margin, cond, label="", max_excluded=0.05, uv_tol=UV_TOL):
                  tri_hits=int((prim >= 0).sum()), df_hits=int((prim == -2).sum()), misses=int(miss.sum()))
     assert not msgs, "%s: %s\n%s" % (label, stats, "\n".join(msgs))
     return stats
+
+
+def check_shadow(got, ref, margin, orc, verts, tris, rays_soa, segs, label="", max_excluded=0.05):
+    """Any-hit parity: occlusion (prim != -1) and the distance-field class
+    (prim == -2) match on decided rays; a reported triangle occluder must be hit
+    by the ray in one of the triangle segments `segs` = [(a, b), (a, b)]."""
+    t, prim = np.asarray(got[0]), np.asarray(got[1])
+    rp = np.asarray(ref[1])
+    dec = margin > MARGIN
+    msgs = []
+    bad = dec & ((prim != -1) != (rp != -1))
+    if bad.any():
+        i = np.nonzero(bad)[0][:5]
+        msgs.append("%d occlusion mismatches, e.g. %s got %s ref %s" % (bad.sum(), i.tolist(), prim[i].tolist(),
+                                                                       rp[i].tolist()))
+    bad = dec & ((prim == -2) != (rp == -2))
+    if bad.any():
+        msgs.append("%d distance-field class mismatches" % bad.sum())
+    tri = np.nonzero(dec & (prim >= 0))[0]
+    for i in tri[:512]:
+        r1 = np.ascontiguousarray(np.asarray(rays_soa)[:, i:i + 1])
+        ok = False
+        for a, b in segs:
+            ai, bi = np.broadcast_to(a, (len(t),))[i], np.broadcast_to(b, (len(t),))[i]
+            if bi < ai:
+                continue
+            h = orc.closest_hit(verts, np.asarray(tris)[prim[i]:prim[i] + 1], r1, ai, bi)
+            ok |= h[1][0] == 0 and abs(h[0][0] - t[i]) <= 1e-5 * max(h[0][0], 0.05)
+        if not ok:
+            msgs.append("ray %d reports triangle %d at t=%s, not hit in the triangle segments" % (i, prim[i], t[i]))
+            break
+    excl = 1.0 - dec.mean()
+    if excl > max_excluded:
+        msgs.append("excluded fraction %.4f" % excl)
+    assert not msgs, label + "\n" + "\n".join(msgs)
+    return dict(n=len(t), excluded=float(excl), occluded=int((prim != -1).sum()), df=int((prim == -2).sum()))

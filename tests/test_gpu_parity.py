@@ -257,3 +257,50 @@ def test_gi_formats_full_launch(hyb, orc, gi, fmt):
         ref = orc.query(sc.verts, sc.tris, deq, g4, sub.soa(), 0.5, tau)
         m, c = orc.margin(sc.verts, sc.tris, deq, g4, sub.soa(), 0.5, tau)
         parity.check(got, ref, m, c, label="gi fmt %d tau %s" % (fmt, tau))
+
+
+# ---------------------------------------------------------------------------
+# shadow-ray query: triangles at both ends, the distance field in between, any hit
+# ---------------------------------------------------------------------------
+
+def shadow_segments(g4, tmax, ts, te):
+    h = np.float32(g4[3])
+    t1 = np.minimum(np.float32(ts) * h, tmax).astype(np.float64)
+    t2 = np.maximum((tmax - np.float32(te) * h).astype(np.float32).astype(np.float64), t1)
+    return [(0.0, t1), (t2, tmax.astype(np.float64))]
+
+
+@pytest.mark.parametrize("taus", [(0.0, 0.0), (1.0, 1.0), (2.0, 4.0), (np.inf, np.inf)])
+def test_tiny_shadow(hyb, orc, tiny, tiny_dev, taus):
+    from paper_2305_07253_amd import workloads as W
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    pts = W.surface_points(sc, 4096, 14)
+    rays, tmax = W.shadow_rays(pts.p, pts.n, 15)
+    s = rays.soa()
+    ts, te = taus
+    got = host(hyb.trace_shadow(tiny_dev["bvh"], tiny_dev["sdf"], to_dev(s), 10.0, ts, te, tmax_ray=to_dev(tmax)))
+    ref = orc.query(sc.verts, sc.tris, grid, g4, s, 10.0, ts, mode=3, tmax_ray=tmax, tau_end=te)
+    m, _ = orc.margin(sc.verts, sc.tris, grid, g4, s, 10.0, ts, mode=3, tmax_ray=tmax, tau_end=te)
+    st = parity.check_shadow(got, ref, m, orc, sc.verts, sc.tris, s, shadow_segments(g4, tmax, ts, te),
+                             label="gpu shadow %s" % (taus,))
+    assert st["occluded"] > 200
+
+
+def test_gi_shadow_full_launch(hyb, orc, gi):
+    """Shadow rays from every G-buffer point to the area light, all 2,073,600
+    in one launch; the fixed-stride sample against the oracle."""
+    from paper_2305_07253_amd import workloads as W
+    sc, g4 = gi["scene"], gi["g4"]
+    gb = W.gbuffer(sc, 1920, 1080)
+    rays, tmax = W.shadow_rays(gb.p, gb.n, 22)
+    sub = rays.subset(gi["sample"])
+    tsub = tmax[gi["sample"]]
+    for ts, te in ((1.0, 1.0), (4.0, 2.0)):
+        out = hyb.trace_shadow(gi["bvh"], gi["sdf"], to_dev(rays.soa()), 10.0, ts, te, tmax_ray=to_dev(tmax))
+        got = [x.cpu().numpy()[gi["sample"]] for x in out]
+        ref = orc.query(sc.verts, sc.tris, gi["oracle_grid"], g4, sub.soa(), 10.0, ts, mode=3, tmax_ray=tsub,
+                        tau_end=te)
+        m, _ = orc.margin(sc.verts, sc.tris, gi["oracle_grid"], g4, sub.soa(), 10.0, ts, mode=3, tmax_ray=tsub,
+                          tau_end=te)
+        parity.check_shadow(got, ref, m, orc, sc.verts, sc.tris, sub.soa(), shadow_segments(g4, tsub, ts, te),
+                            label="gi shadow %s %s" % (ts, te))

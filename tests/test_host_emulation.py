@@ -122,3 +122,22 @@ def test_sdf_build_matches_oracle(emu, orc, tiny):
     assert np.all(np.abs(got.astype(np.float64) - ref) <= ulp)
     far = np.abs(ref) > 1e-6
     assert np.array_equal(np.sign(got[far]), np.sign(ref[far]))
+
+
+@pytest.mark.parametrize("taus", [(0.0, 0.0), (1.0, 1.0), (2.0, 4.0), (np.inf, np.inf)])
+def test_shadow_query_matches_oracle(emu, orc, tiny, taus):
+    from paper_2305_07253_amd import workloads as W
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    pts = W.surface_points(sc, 2048, 14)
+    rays, tmax = W.shadow_rays(pts.p, pts.n, 15)
+    s = rays.soa()
+    ts, te = taus
+    got = emu.trace(sc.verts, sc.tris, grid, g4, s, 10.0, ts, mode=3, tmax_ray=tmax, tau_end=te)
+    ref = orc.query(sc.verts, sc.tris, grid, g4, s, 10.0, ts, mode=3, tmax_ray=tmax, tau_end=te)
+    m, c = orc.margin(sc.verts, sc.tris, grid, g4, s, 10.0, ts, mode=3, tmax_ray=tmax, tau_end=te)
+    h = np.float32(g4[3])
+    t1 = np.minimum(np.float32(ts) * h, tmax).astype(np.float64)
+    t2 = np.maximum((tmax - np.float32(te) * h).astype(np.float32).astype(np.float64), t1)
+    st = parity.check_shadow(got, ref, m, orc, sc.verts, sc.tris, s, [(0.0, t1), (t2, tmax.astype(np.float64))],
+                             label="emu shadow %s" % (taus,))
+    assert st["occluded"] > 100

@@ -539,3 +539,44 @@ def test_quantized_interpolant_stays_continuous(orc, tiny):
             a = orc.df_value(deq, g4, (x - 1e-12, y, z))
             b = orc.df_value(deq, g4, (x + 1e-12, y, z))
             assert abs(a - b) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# shadow-ray query (any hit, three segments)
+# ---------------------------------------------------------------------------
+
+def shadow_set(tiny):
+    pts = W.surface_points(tiny["scene"], 2048, 14)
+    return W.shadow_rays(pts.p, pts.n, 15)
+
+
+def test_shadow_limits_and_decomposition(orc, tiny):
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    rays, tmax = shadow_set(tiny)
+    s = rays.soa()
+    occ = lambda r: r[1] != -1
+    bvh = orc.query(sc.verts, sc.tris, grid, g4, s, 10.0, 0.0, mode=1, tmax_ray=tmax)
+    df = orc.query(sc.verts, sc.tris, grid, g4, s, 10.0, 0.0, mode=2, tmax_ray=tmax)
+    a = orc.query(sc.verts, sc.tris, grid, g4, s, 10.0, np.inf, mode=3, tmax_ray=tmax, tau_end=np.inf)
+    b = orc.query(sc.verts, sc.tris, grid, g4, s, 10.0, 0.0, mode=3, tmax_ray=tmax, tau_end=0.0)
+    assert np.array_equal(occ(a), occ(bvh)) and np.array_equal(a[1], bvh[1])
+    assert np.array_equal(occ(b), occ(df)) and np.array_equal(b[0], df[0])
+    h = np.float32(g4[3])
+    for t_s, t_e in ((1.0, 1.0), (2.0, 0.5), (4.0, 4.0)):
+        r = orc.query(sc.verts, sc.tris, grid, g4, s, 10.0, t_s, mode=3, tmax_ray=tmax, tau_end=t_e)
+        t1 = np.minimum(np.float32(t_s) * h, tmax).astype(np.float64)  # tmin = 0
+        t2 = np.maximum((tmax - np.float32(t_e) * h).astype(np.float32).astype(np.float64), t1)
+        mid = np.where(t2 > t1, orc.df_hit(grid, g4, s, t1, t2), np.inf)  # a zero-length DF part is not traced
+        first = orc.closest_hit(sc.verts, sc.tris, s, 0.0, t1)
+        last = orc.closest_hit(sc.verts, sc.tris, s, t2, tmax.astype(np.float64))
+        expect = np.isfinite(mid) | (first[1] >= 0) | (last[1] >= 0)
+        assert np.array_equal(occ(r), expect)
+        assert np.array_equal(r[1] == -2, np.isfinite(mid))
+    # a clear segment: rays in the empty upper part of a room-only scene reach the light
+    rv, rf = W._box_mesh(1)
+    empty = mesh_scene(0.5 + 0.5 * rv, rf[:, ::-1], [W.KIND_ROOM], [0], [12])
+    eg = orc.sdf_grid(empty, g4, 32)
+    pts = np.random.default_rng(2).uniform(0.3, 0.7, (256, 3))
+    er, et = W.shadow_rays(pts, np.tile([0, 1.0, 0], (256, 1)), 3)
+    r = orc.query(empty.verts, empty.tris, eg, g4, er.soa(), 10.0, 1.0, mode=3, tmax_ray=et, tau_end=1.0)
+    assert np.all(r[1] == -1)
