@@ -196,6 +196,25 @@ hyb_status hyb_trace_shadow(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int6
 hyb_status hyb_trace_counters(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax,
                               float threshold, int32_t mode, hyb_hits* hits, int32_t* counts, void* stream);
 
+/* Backward of the distance-field hit distance with respect to the grid
+ * samples (implicit differentiation of g(t*; theta) = 0 at the first root t*):
+ *     d t* / d theta_j = -w_j(p*) / (grad f~(p*) . d),   p* = o + t* d,
+ * for the 8 corners j of the cell holding p* (w_j the trilinear weights), 0 for
+ * every other sample.  The ray path is not stored: each ray's hit point is
+ * recomputed from t_hit.  A ray without a crossing (t_hit = +inf, or a hit at
+ * the start of its segment, where the segment began at or below zero and t*
+ * does not move with theta) contributes nothing.
+ *   rays, n, tmax  the rays and segment of the forward hyb_trace_df call
+ *   t_hit          device, n floats: the forward result
+ *   grad_t         device, n floats: d loss / d t_hit
+ *   grad_grid      device, n_grid^3 floats (x fastest): accumulated into (+=)
+ * The sdf must be FP32 (HYB_SDF_F32).  Accumulation uses float atomics: sums
+ * agree across runs up to FP32 rounding of the order of additions.
+ * Errors: HYB_ERR_INVALID_ARG for NULL pointers, n < 0, NaN/negative tmax;
+ * HYB_ERR_UNSUPPORTED for a compact-format sdf. */
+hyb_status hyb_df_backward(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, const float* t_hit,
+                           const float* grad_t, float* grad_grid, void* stream);
+
 hyb_status hyb_bvh_destroy(hyb_bvh bvh);
 hyb_status hyb_sdf_destroy(hyb_sdf sdf);
 

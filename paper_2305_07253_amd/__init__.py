@@ -74,6 +74,7 @@ def lib() -> ctypes.CDLL:
             "hyb_trace_df": [P, P, i64, f32, P, P],
             "hyb_trace_counters": [P, P, P, i64, f32, f32, i32, P, P, P],
             "hyb_trace_shadow": [P, P, P, i64, f32, f32, f32, P, P],
+            "hyb_df_backward": [P, P, i64, f32, P, P, P, P],
             "hyb_bvh_destroy": [P],
             "hyb_sdf_destroy": [P],
         }
@@ -291,6 +292,20 @@ def trace_shadow(bvh: Bvh, sdf: Sdf, rays, tmax: float, threshold_start: float, 
                                                       threshold_start, threshold_end, ctypes.byref(h),
                                                       _stream(stream)))
     return out
+
+
+def df_backward(sdf: Sdf, rays, tmax: float, t_hit, grad_t, grad_grid, tmin=None, tmax_ray=None, stream=None):
+    """grad_grid += d loss / d samples for the DF hits t_hit of hyb_trace_df on
+    the same rays and segment (implicit differentiation at the hit)."""
+    torch = _torch()
+    _query_args(tmax, None)
+    r, n = _rays_struct(rays, tmin, tmax_ray)
+    for x, m in ((t_hit, n), (grad_t, n), (grad_grid, sdf.n ** 3)):
+        if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.numel() == m):
+            raise ValueError("t_hit, grad_t (n) and grad_grid (n_grid^3) must be contiguous float32 CUDA tensors")
+    _check("hyb_df_backward", lib().hyb_df_backward(sdf.handle, ctypes.byref(r), n, tmax, _ptr(t_hit), _ptr(grad_t),
+                                                    _ptr(grad_grid), _stream(stream)))
+    return grad_grid
 
 
 def trace_counters(bvh, sdf, rays, tmax: float, threshold: float, mode: int = MODE_COMBINED, tmin=None,

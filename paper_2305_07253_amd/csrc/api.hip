@@ -355,6 +355,20 @@ hyb_status hyb_trace_shadow(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int6
     return from_hip(hyb::launch_trace(hyb::kShadow, false, a, static_cast<hipStream_t>(stream)));
 }
 
+hyb_status hyb_df_backward(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, const float* t_hit,
+                           const float* grad_t, float* grad_grid, void* stream) {
+    if (!sdf || n < 0 || std::isnan(tmax) || tmax < 0.0f) return HYB_ERR_INVALID_ARG;
+    if (n == 0) return HYB_OK;
+    if (!valid_rays(rays) || !t_hit || !grad_t || !grad_grid) return HYB_ERR_INVALID_ARG;
+    if (sdf->fmt != HYB_SDF_F32) return HYB_ERR_UNSUPPORTED;
+    if (!same_device(sdf->device)) return HYB_ERR_INVALID_ARG;
+    hyb::TraceArgs a;
+    hyb_hits none = {nullptr, nullptr, nullptr, nullptr};
+    fill_trace_args(a, rays, &none, n, tmax, 0.0f);
+    fill_scene(a, nullptr, sdf);
+    return from_hip(hyb::launch_df_backward(a, t_hit, grad_t, grad_grid, static_cast<hipStream_t>(stream)));
+}
+
 hyb_status hyb_trace_counters(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, float threshold,
                               int32_t mode, hyb_hits* hits, int32_t* counts, void* stream) {
     if (mode < 0 || mode > 3 || std::isnan(threshold) || threshold < 0.0f) return HYB_ERR_INVALID_ARG;

@@ -517,6 +517,43 @@ HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx
     }
 }
 
+// Implicit derivative of a distance-field hit: for the ray's hit t_hit on its
+// segment [a, b], the 8 node indices of the cell holding p = o + t_hit d and
+// d t_hit / d sample = -w_j / (grad f~(p) . d).  Returns false when the ray has
+// no crossing (no hit, a hit at the clipped segment start, or a vanishing
+// directional derivative).
+HYB_HD bool df_hit_gradient(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz, float a,
+                            float b, float t_hit, int64_t node[8], float dt[8]) {
+    if (!(t_hit < __builtin_inff())) return false;
+    DfRay r;
+    if (!df_init(g, ox, oy, oz, dx, dy, dz, a, b, r) || !(t_hit > r.t)) return false;
+    const int nm2 = g.n - 2;
+    const double X = fma((double)t_hit, r.qx, r.px), Y = fma((double)t_hit, r.qy, r.py), Z = fma((double)t_hit, r.qz, r.pz);
+    const int ci = min(max((int)floor(X), 0), nm2), cj = min(max((int)floor(Y), 0), nm2), ck = min(max((int)floor(Z), 0), nm2);
+    const float fx = (float)(X - ci), fy = (float)(Y - cj), fz = (float)(Z - ck);
+    float f[8];
+    corners<kF32>(g, ci, cj, ck, f);
+    // gradient of the interpolant in cell units, then along d (per unit t)
+    const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+    for (int c = 0; c < 8; ++c) {
+        const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+        gx += f[c] * (bx ? 1.0f : -1.0f) * wy[by] * wz[bz];
+        gy += f[c] * wx[bx] * (by ? 1.0f : -1.0f) * wz[bz];
+        gz += f[c] * wx[bx] * wy[by] * (bz ? 1.0f : -1.0f);
+    }
+    const float slope = gx * r.qxf + gy * r.qyf + gz * r.qzf;
+    if (slope == 0.0f) return false;
+    const float inv = -1.0f / slope;
+    const int64_t n = g.n;
+    for (int c = 0; c < 8; ++c) {
+        const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+        node[c] = (int64_t)(ci + bx) + n * ((int64_t)(cj + by) + n * (int64_t)(ck + bz));
+        dt[c] = wx[bx] * wy[by] * wz[bz] * inv;
+    }
+    return true;
+}
+
 // Gradient bound of the trilinear interpolant inside one cell (corners f):
 // each partial derivative is a convex blend of the cell's four edge differences
 // along that axis (divided by h), so |grad| <= sqrt(mx^2 + my^2 + mz^2) / h.

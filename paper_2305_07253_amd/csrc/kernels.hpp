@@ -40,6 +40,10 @@ hipError_t launch_trace(int mode, bool counters, const TraceArgs& a, hipStream_t
 hipError_t launch_quantize(int fmt, const float* in, int32_t n, void* out, float* scales, float* deq,
                            hipStream_t stream);
 
+// Scatter of d loss / d grid sample for distance-field hits (hyb_df_backward).
+hipError_t launch_df_backward(const TraceArgs& a, const float* t_hit, const float* grad_t, float* grad_grid,
+                              hipStream_t stream);
+
 struct SdfBuildArgs {
     const float4* nodes;
     const float4* tris;

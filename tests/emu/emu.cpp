@@ -14,6 +14,9 @@
 //         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays], tmax f32[n_rays]
 // what 0 (trace): output t f32[n], prim i32[n], u f32[n], v f32[n], counts i32[3n]
 // what 1 (sdf):   output f32[N^3] signed distances of the grid nodes
+// what 2 (grad):  input as what 0 plus t_hit f32[n_rays] after the ray arrays;
+//                 output per ray i64[8] node indices (-1: no contribution) and
+//                 f32[8] d t / d sample
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -43,13 +46,14 @@ int main(int argc, char** argv) {
     const long long nb = (N + hyb::kScaleBlock - 1) / hyb::kScaleBlock;
     auto verts = rd<float>(f, 3 * nv);
     auto tris = rd<int32_t>(f, 3 * nt);
-    std::vector<float> grid = what == 0 && N > 0 ? rd<float>(f, N * N * N) : std::vector<float>();
+    std::vector<float> grid = what != 1 && N > 0 ? rd<float>(f, N * N * N) : std::vector<float>();
     std::vector<_Float16> g16 = what == 0 && N > 0 && fmt == 1 ? rd<_Float16>(f, N * N * N) : std::vector<_Float16>();
     std::vector<int8_t> g8 = what == 0 && N > 0 && fmt == 2 ? rd<int8_t>(f, N * N * N) : std::vector<int8_t>();
     std::vector<float> scales = what == 0 && N > 0 && fmt == 2 ? rd<float>(f, nb * nb * nb) : std::vector<float>();
     auto rays = rd<float>(f, 6 * n);
     auto tmin = (has_tmin & 1) ? rd<float>(f, n) : std::vector<float>();
     auto tmaxr = (has_tmin & 2) ? rd<float>(f, n) : std::vector<float>();
+    auto thit = what == 2 ? rd<float>(f, n) : std::vector<float>();
     fclose(f);
 
     hyb::BvhHost bvh;
@@ -114,6 +118,24 @@ int main(int argc, char** argv) {
     a.tmax = par[0];
     a.tau = par[1];
     a.n = n;
+    if (what == 2) {
+        const hyb::Grid g = {grid.data(), nullptr, (int)N, 0, par[2], par[3], par[4], par[5], inv_h, a.inv_l,
+                             __builtin_inff(), 1.0 / (double)par[5]};
+        std::vector<long long> nodes(8 * n, -1);
+        std::vector<float> dts(8 * n, 0.0f);
+        for (long long i = 0; i < n; ++i) {
+            const float t0 = (has_tmin & 1) ? tmin[i] : 0.0f;
+            const float t1 = (has_tmin & 2) ? fminf(tmaxr[i], par[0]) : par[0];
+            int64_t nd[8];
+            float dt[8];
+            if (hyb::df_hit_gradient(g, a.ox[i], a.oy[i], a.oz[i], a.dx[i], a.dy[i], a.dz[i], t0, t1, thit[i], nd, dt))
+                for (int c = 0; c < 8; ++c) { nodes[8 * i + c] = nd[c]; dts[8 * i + c] = dt[c]; }
+        }
+        fwrite(nodes.data(), 8, 8 * n, o);
+        fwrite(dts.data(), 4, 8 * n, o);
+        fclose(o);
+        return 0;
+    }
     std::vector<int> stack(hyb::kLdsDepth);
     for (long long i = 0; i < n; ++i) {
         if (mode == 1) hyb::trace_ray<hyb::kBvhOnly, hyb::kF32, true>(a, i, stack.data(), 1);

@@ -97,3 +97,19 @@ def sdf(verts, tris, grid4, N, exterior_solid=True):
     par = [0, 0, g4[0], g4[1], g4[2], g4[3], 1.0 if exterior_solid else 0.0, 0]
     raw = _run(hdr, par, [np.asarray(verts, np.float32), np.asarray(tris, np.int32)], 4 * N ** 3)
     return raw.view(np.float32).reshape(N, N, N)
+
+
+def df_grad(grid, grid4, rays_soa, t_hit, tmax, tmin=None):
+    """The backward kernel's per-ray (node[8], dt[8]) for the hits t_hit."""
+    rays_soa = np.ascontiguousarray(rays_soa, dtype=np.float32)
+    n = rays_soa.shape[1]
+    N = np.asarray(grid).shape[-1]
+    g4 = np.asarray(grid4, np.float32)
+    arrays = [np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32), np.asarray(grid, np.float32), rays_soa]
+    if tmin is not None:
+        arrays.append(np.asarray(tmin, np.float32))
+    arrays.append(np.asarray(t_hit, np.float32))
+    hdr = [2, n, 0, 0, N, 1 if tmin is not None else 0, 2, 0]
+    par = [tmax, 0, g4[0], g4[1], g4[2], g4[3], 0, 0]
+    raw = _run(hdr, par, arrays, 64 * n + 32 * n)
+    return raw[:64 * n].view(np.int64).reshape(n, 8), raw[64 * n:].view(np.float32).reshape(n, 8)

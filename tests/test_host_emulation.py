@@ -141,3 +141,24 @@ def test_shadow_query_matches_oracle(emu, orc, tiny, taus):
     st = parity.check_shadow(got, ref, m, orc, sc.verts, sc.tris, s, [(0.0, t1), (t2, tmax.astype(np.float64))],
                              label="emu shadow %s" % (taus,))
     assert st["occluded"] > 100
+
+
+def test_df_gradient_matches_oracle(emu, orc, tiny):
+    """The backward kernel's per-ray implicit derivatives against the oracle's
+    FP64 ones (O-6) at the same hits."""
+    grid, g4 = tiny["grid"], tiny["grid4"]
+    s = tiny["free"].soa()
+    t = orc.df_hit(grid, g4, s, 0.0, 2.0)
+    m, c = orc.margin(None, np.zeros((0, 3)), grid, g4, s, 2.0, 0.0, mode=orc.MODE_DF)
+    nodes, dt = emu.df_grad(grid, g4, s, t.astype(np.float32), 2.0)
+    rn, rdt = orc.df_grad(grid, g4, s, t.astype(np.float32).astype(np.float64), 0.0, 2.0)
+    ok = (m > 1e-5) & (c > 1e-2)
+    # away from cell faces both sides pick the same cell
+    p = tiny["free"].o.astype(np.float64) + np.where(np.isfinite(t), t, 0)[:, None] * tiny["free"].d.astype(np.float64)
+    x = (p - np.float64(g4[0])) / np.float64(g4[3])
+    ok &= np.abs(x - np.round(x)).min(axis=1) > 1e-4  # most free rays end on walls, which lie on node planes
+    assert ok.sum() > 300
+    assert np.array_equal(nodes[ok], rn[ok])
+    assert np.all(np.abs(dt[ok] - rdt[ok]) <= 1e-4 * np.maximum(np.abs(rdt[ok]).max(axis=1, keepdims=True), 1.0))
+    # rays whose hit is the start of their segment contribute nothing on either side
+    assert np.array_equal(nodes[:, 0] == -1, rn[:, 0] == -1)
