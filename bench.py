@@ -99,6 +99,15 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiling driver: a 256 MiB copy probe, then --steps launches of the combined, "
                          "triangle-only and DF-only kernels; no sweep, no JSON line")
+    ap.add_argument("--config", default="gi", choices=["gi", "diff", "precision", "batch", "shadow"],
+                    help="gi: the headline combined-query benchmark (one JSON line with value); the others print "
+                         "their own JSON line for the differentiation, precision, batching and shadow workloads")
+    ap.add_argument("--adam-steps", type=int, default=200)
+    ap.add_argument("--lr-scale", type=float, default=0.002, help="Adam learning rate in voxels (diff config)")
+    ap.add_argument("--loss", default="dfhit", choices=["both", "dfhit"],
+                    help="diff config: MSE over rays where both hit, or over every DF hit with triangle misses "
+                         "targeting tmax (pulls false DF hits out)")
+    ap.add_argument("--oracle-sample", type=int, default=2048, help="precision config: rays checked by the oracle")
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     args = ap.parse_args()
@@ -112,6 +121,8 @@ def main():
     from paper_2305_07253_amd import workloads as W
 
     hyb.lib()
+    if args.config != "gi":
+        return run_extra(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
@@ -266,6 +277,184 @@ def main():
         "timed_wall_s": wall,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_extra(args):
+    import torch
+    import paper_2305_07253_amd as hyb
+    from paper_2305_07253_amd import workloads as W
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    if args.config == "diff":
+        line = bench_diff(args, torch, hyb, W, dev, stream)
+    elif args.config == "precision":
+        line = bench_precision(args, torch, hyb, W, dev, stream)
+    else:
+        raise SystemExit("config %s not implemented" % args.config)
+    print(json.dumps(line), flush=True)
+
+
+def oracle_grid_sparse(oracle, scene, g4, n, rays, tmax):
+    """The oracle's own exact samples at every node of the cells the rays'
+    segments [0, tmax] can cross (found by sampling each segment every h/16 and
+    taking the neighbouring cells too); NaN elsewhere, so a read outside shows."""
+    h = np.float64(g4[3])
+    lo = g4[:3].astype(np.float64)
+    ts = np.arange(0.0, tmax + h / 16, h / 16)
+    cells = []
+    o, d = rays.o.astype(np.float64), rays.d.astype(np.float64)
+    for c0 in range(0, rays.n, 256):
+        log("oracle cells: rays %d / %d" % (c0, rays.n))
+        p = o[c0:c0 + 256, None, :] + ts[None, :, None] * d[c0:c0 + 256, None, :]
+        c = np.floor((p - lo) / h).astype(np.int64).reshape(-1, 3)
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    cc = np.clip(c + np.array([dx, dy, dz]), 0, n - 2)
+                    cells.append(np.unique(cc[:, 0] + n * (cc[:, 1] + n * cc[:, 2])))
+    cells = np.unique(np.concatenate(cells))
+    ci, cj, ck = cells % n, (cells // n) % n, cells // (n * n)
+    nodes = np.unique(np.concatenate([(ci + dx) + n * ((cj + dy) + n * (ck + dz))
+                                      for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]))
+    grid = np.full(n ** 3, np.nan, dtype=np.float32)
+    step = 1 << 18
+    for c0 in range(0, len(nodes), step):
+        log("oracle samples: %d / %d nodes" % (c0, len(nodes)))
+        grid[nodes[c0:c0 + step]] = oracle.sdf_nodes(scene, g4, n, nodes=nodes[c0:c0 + step]).astype(np.float32)
+    return grid.reshape(n, n, n), len(nodes)
+
+
+def bench_precision(args, torch, hyb, W, dev, stream):
+    """2M-triangle scene, 256^3 grid stored FP32 / FP16 / int8 + block scales,
+    4 rays per pixel at 1080p; rays/s per format and each format's t error
+    against the FP64 oracle on the exact grid (a fixed-stride ray sample)."""
+    import oracle
+    oracle.build()
+    t0 = time.time()
+    scene = W.precision_scene(3)
+    g4 = W.room_grid(256)
+    h = float(g4[3])
+    gb = W.gbuffer(scene, args.width, args.height)
+    rays = W.gbuffer_rays(gb, 31, spp=4)
+    log("precision workload: %d triangles, %d rays (%.1fs)" % (scene.n_tris, rays.n, time.time() - t0))
+    t0 = time.time()
+    bvh = hyb.build_bvh(scene.verts, scene.tris)
+    t_bvh = time.time() - t0
+    t0 = time.time()
+    f32 = hyb.build_sdf(bvh, 256, g4)
+    torch.cuda.synchronize()
+    t_sdf = time.time() - t0
+    vals = hyb.sdf_read(f32).reshape(-1).contiguous()
+    grids = {"f32": f32, "f16": hyb.sdf_from_grid(vals, g4, fmt=hyb.SDF_F16),
+             "i8": hyb.sdf_from_grid(vals, g4, fmt=hyb.SDF_I8_BRICK)}
+    log("bvh %.1fs (%d nodes, depth %d), sdf 256^3 %.2fs" % (t_bvh, bvh.n_nodes, bvh.depth, t_sdf))
+    R = torch.from_numpy(rays.soa()).to(dev)
+    out = hyb.alloc_hits(rays.n)
+    idx = np.linspace(0, rays.n - 1, args.oracle_sample).astype(np.int64)
+    sub = rays.subset(idx)
+    t0 = time.time()
+    og, n_nodes = oracle_grid_sparse(oracle, scene, g4, 256, sub, TMAX)
+    log("oracle: exact samples at %d nodes (%.1fs)" % (n_nodes, time.time() - t0))
+    res = {}
+    for tau in (0.0, 1.0):
+        ref = oracle.query(scene.verts, scene.tris, og, g4, sub.soa(), TMAX, tau)
+        assert np.all(np.isfinite(ref[0]) | (ref[1] == -1)), "oracle read a node outside the sampled cells"
+        for name, sdf in grids.items():
+            ms = time_launches(lambda: hyb.trace(bvh, sdf, R, TMAX, tau, out=out), stream, 10, 2)
+            t = out[0].cpu().numpy()[idx].astype(np.float64)
+            prim = out[1].cpu().numpy()[idx]
+            same = (prim == ref[1]) | ((prim >= 0) & (ref[1] >= 0))
+            both = np.isfinite(t) & np.isfinite(ref[0])
+            rel = np.abs(t - ref[0])[both] / np.maximum(ref[0][both], 0.05)
+            res["%s_tau%s" % (name, tau)] = dict(
+                ms=ms, mrays_s=rays.n / ms / 1e3, class_agreement=float(same.mean()),
+                hit_agreement=float((np.isfinite(t) == np.isfinite(ref[0])).mean()),
+                rel_t_err_mean=float(rel.mean()), rel_t_err_p99=float(np.percentile(rel, 99)),
+                rel_t_err_max=float(rel.max()), abs_t_err_over_h_p99=float(np.percentile(rel * np.maximum(
+                    ref[0][both], 0.05) / h, 99)))
+            log("%s tau=%s: %.3f ms (%.0f Mrays/s), class agreement %.5f, rel t err mean %.2e p99 %.2e" % (
+                name, tau, ms, rays.n / ms / 1e3, same.mean(), rel.mean(), np.percentile(rel, 99)))
+    return {"config": "precision", "workload": "%d-triangle room, 256^3 grid (h=1/251), %d rays (4 per pixel, "
+            "1920x1080 G-buffer), tmax 0.5" % (scene.n_tris, rays.n), "oracle_sample": int(len(idx)),
+            "grid_bytes": {"f32": 4 * 256 ** 3, "f16": 2 * 256 ** 3, "i8": 256 ** 3 + 4 * 32 ** 3},
+            "results": res}
+
+
+def bench_diff(args, torch, hyb, W, dev, stream):
+    """Refit the DF against triangle hits: forward DF-only hit t from p + h n on
+    [0, 0.5], loss = MSE against triangle-only t from the same origins over rays
+    where both hit, backward by implicit differentiation, Adam on the samples."""
+    from paper_2305_07253_amd.autograd import df_hit
+    scene = W.gi_scene(2)
+    g4 = W.room_grid(128)
+    h = float(g4[3])
+    gb = W.gbuffer(scene, 1024, 1024)
+    rays = W.rebias(W.gbuffer_rays(gb, 41), gb, h)
+    held = W.rebias(W.gbuffer_rays(gb, 42), gb, h)
+    bvh = hyb.build_bvh(scene.verts, scene.tris)
+    theta0 = hyb.sdf_read(hyb.build_sdf(bvh, 128, g4)).reshape(-1).contiguous()
+    R = torch.from_numpy(rays.soa()).to(dev)
+    Rh = torch.from_numpy(held.soa()).to(dev)
+    target = hyb.trace_bvh(bvh, R, TMAX)[0]
+    target_h = hyb.trace_bvh(bvh, Rh, TMAX)[0]
+
+    def artefact_rate(theta, Rx, tref):
+        t = hyb.trace_df(hyb.sdf_from_grid(theta.detach().contiguous(), g4), Rx, TMAX)[0]
+        hit, hit_ref = torch.isfinite(t), torch.isfinite(tref)
+        both = hit & hit_ref
+        bad = (hit != hit_ref).sum() + ((t - tref).abs()[both] > h).sum()
+        return float(bad) / t.numel(), float(((t - tref).abs()[both] / h).mean())
+
+    goal = torch.where(torch.isfinite(target), target, torch.full_like(target, TMAX))
+
+    def loss_of(theta):
+        t = df_hit(theta, g4, R, TMAX)
+        if args.loss == "both":
+            use = torch.isfinite(t) & torch.isfinite(target)
+            d = torch.where(use, t - target, torch.zeros_like(t))
+        else:
+            use = torch.isfinite(t)
+            d = torch.where(use, t - goal, torch.zeros_like(t))
+        return (d * d).sum() / use.sum().clamp(min=1)
+
+    before = artefact_rate(theta0, Rh, target_h)
+    theta = theta0.clone().requires_grad_(True)
+    opt = torch.optim.Adam([theta], lr=args.lr_scale * h)
+    # time forward + backward (+ Adam) per step
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for it in range(args.adam_steps):
+        opt.zero_grad()
+        loss = loss_of(theta)
+        loss.backward()
+        opt.step()
+        losses.append(float(loss.detach()))
+        if it % 50 == 0:
+            log("adam step %d loss %.3e" % (it, losses[-1]))
+    torch.cuda.synchronize()
+    step_ms = (time.time() - t0) * 1e3 / max(args.adam_steps, 1)
+    after = artefact_rate(theta, Rh, target_h)
+    # kernel times of one forward and one backward on the final grid
+    sdf = hyb.sdf_from_grid(theta.detach().contiguous(), g4)
+    out = hyb.alloc_hits(rays.n)
+    ms_fwd = time_launches(lambda: hyb.trace_df(sdf, R, TMAX, out=out), stream, 20, 2)
+    grad = torch.zeros(128 ** 3, device=dev)
+    ones = torch.ones(rays.n, device=dev)
+    ms_bwd = time_launches(lambda: hyb.df_backward(sdf, R, TMAX, out[0], ones, grad), stream, 20, 2)
+    log("refit: loss %.3e -> %.3e; artefacts %.4f -> %.4f; step %.2f ms" % (losses[0], losses[-1], before[0],
+                                                                            after[0], step_ms))
+    return {"config": "differentiation", "workload": "GI scene (%d triangles), 128^3 FP32 learnable grid, "
+            "1024x1024 G-buffer diffuse rays from p + h n, tmax 0.5, loss MSE vs triangle hits (%s)" % (
+                scene.n_tris, args.loss),
+            "rays": rays.n, "adam_steps": args.adam_steps, "lr": args.lr_scale * h, "loss": args.loss,
+            "lipschitz_after": sdf.lipschitz,
+            "loss_first": losses[0] if losses else None, "loss_last": losses[-1] if losses else None,
+            "heldout_artefact_rate_before": before[0], "heldout_artefact_rate_after": after[0],
+            "heldout_mean_dt_over_h_before": before[1], "heldout_mean_dt_over_h_after": after[1],
+            "ms_per_adam_step": step_ms, "forward_kernel_ms": ms_fwd, "backward_kernel_ms": ms_bwd,
+            "forward_mrays_s": rays.n / ms_fwd / 1e3, "backward_mrays_s": rays.n / ms_bwd / 1e3}
 
 
 if __name__ == "__main__":
