@@ -108,6 +108,9 @@ def main():
                     help="diff config: MSE over rays where both hit, or over every DF hit with triangle misses "
                          "targeting tmax (pulls false DF hits out)")
     ap.add_argument("--oracle-sample", type=int, default=2048, help="precision config: rays checked by the oracle")
+    ap.add_argument("--max-error", type=float, default=0.03,
+                    help="batch config: per-scene cap on the fraction of rays that differ from triangles-only")
+    ap.add_argument("--scenes", type=int, default=64, help="batch config: number of scenes")
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     args = ap.parse_args()
@@ -290,6 +293,8 @@ def run_extra(args):
         line = bench_diff(args, torch, hyb, W, dev, stream)
     elif args.config == "precision":
         line = bench_precision(args, torch, hyb, W, dev, stream)
+    elif args.config == "batch":
+        line = bench_batch(args, torch, hyb, W, dev, stream)
     else:
         raise SystemExit("config %s not implemented" % args.config)
     print(json.dumps(line), flush=True)
@@ -455,6 +460,102 @@ def bench_diff(args, torch, hyb, W, dev, stream):
             "heldout_mean_dt_over_h_before": before[1], "heldout_mean_dt_over_h_after": after[1],
             "ms_per_adam_step": step_ms, "forward_kernel_ms": ms_fwd, "backward_kernel_ms": ms_bwd,
             "forward_mrays_s": rays.n / ms_fwd / 1e3, "backward_mrays_s": rays.n / ms_bwd / 1e3}
+
+
+def bench_batch(args, torch, hyb, W, dev, stream):
+    """Many scenes of uneven size: one persistent graph launch against one
+    launch per scene, both at the autotuned thresholds."""
+    specs = W.batch_specs(4, args.scenes)
+    items, meta = [], []
+    t0 = time.time()
+    for k, sp in enumerate(specs):
+        scene = W.batch_scene(sp)
+        bvh = hyb.build_bvh(scene.verts, scene.tris)
+        sdf = hyb.build_sdf(bvh, sp.n_grid, W.room_grid(sp.n_grid))
+        rays = W.gbuffer_rays(W.gbuffer(scene, sp.width, sp.height), sp.seed)
+        items.append(dict(bvh=bvh, sdf=sdf, rays=torch.from_numpy(rays.soa()).to(dev), tmax=TMAX, threshold=1.0))
+        meta.append(dict(tris=scene.n_tris, rays=rays.n, grid=sp.n_grid))
+        log("scene %d/%d: %d triangles, %d rays, grid %d^3 (%.0fs)" % (k + 1, len(specs), scene.n_tris, rays.n,
+                                                                       sp.n_grid, time.time() - t0))
+    torch.cuda.synchronize()
+    n_rays = sum(m["rays"] for m in meta)
+    n_tris = sum(m["tris"] for m in meta)
+
+    batch = hyb.Batch(items)
+    default_cfg = batch.config
+    ms_default = time_launches(lambda: batch.launch(), stream, args.reps, 2)
+    log("batch, default config %s, threshold 1: %.3f ms (%.0f Mrays/s)" % (default_cfg, ms_default,
+                                                                           n_rays / ms_default / 1e3))
+    t0 = time.time()
+    err, tuned_ms = batch.tune(max_error_rate=args.max_error, reps=3)
+    tune_s = time.time() - t0
+    cfg = batch.config
+    taus = [batch.threshold(k) for k in range(len(items))]
+    log("tuned in %.1fs: config %s, %.3f ms; thresholds %s" % (tune_s, cfg, tuned_ms, taus))
+
+    def per_scene():
+        for k, it in enumerate(items):
+            hyb.trace(it["bvh"], it["sdf"], it["rays"], TMAX, taus[k], out=batch.outs[k])
+
+    ms_loop = time_launches(per_scene, stream, args.reps, 2)
+    # the same launches captured in one graph (no host gaps between them)
+    ms_loop_graph = None
+    try:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            per_scene()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            per_scene()
+        torch.cuda.synchronize()
+        ms_loop_graph = time_launches(g.replay, stream, args.reps, 2)
+    except Exception as e:  # reported, not fatal: the persistent batch is the measured path
+        log("per-scene graph capture failed: %s" % e)
+    ms_eager = time_launches(lambda: batch.launch(graph=False), stream, args.reps, 2)
+    for _ in range(args.warmup):
+        batch.launch()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.time()
+    start.record(stream)
+    for _ in range(args.steps):
+        batch.launch()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - wall0
+    ms_graph = start.elapsed_time(stop) / args.steps
+    log("graph %.3f ms, eager %.3f ms, %d per-scene launches %.3f ms (captured: %s ms)" % (
+        ms_graph, ms_eager, len(items), ms_loop, ms_loop_graph))
+
+    # algorithmic bytes at the tuned thresholds (same accounting as the GI line)
+    total_bytes = 0.0
+    for k, it in enumerate(items):
+        _, cnt = hyb.trace_counters(it["bvh"], it["sdf"], it["rays"], TMAX, taus[k], hyb.MODE_COMBINED)
+        c = cnt.double().sum(dim=0).cpu().numpy()
+        total_bytes += 40.0 * meta[k]["rays"] + 64 * c[0] + 48 * c[1] + 32 * c[2]
+    achieved = total_bytes / (ms_graph * 1e-3) / 1e9
+    hist = {}
+    for t in taus:
+        key = "inf" if math.isinf(t) else t
+        hist[key] = hist.get(key, 0) + 1
+    return {
+        "config": "batch",
+        "workload": "%d seeded scenes, %d triangles in all (%d to %d, log-uniform), grids 32^3 to 128^3, %d "
+                    "G-buffer diffuse rays in all (%d to %d per scene, log-uniform), tmax 0.5" % (
+                        len(items), n_tris, min(m["tris"] for m in meta), max(m["tris"] for m in meta), n_rays,
+                        min(m["rays"] for m in meta), max(m["rays"] for m in meta)),
+        "metric": "Mrays/s, whole batch in one graph launch", "value": n_rays / ms_graph / 1e3, "unit": "Mrays/s",
+        "ms_graph": ms_graph, "ms_eager": ms_eager, "ms_per_scene_launches": ms_loop,
+        "speedup_vs_per_scene_launches": ms_loop / ms_graph, "ms_per_scene_launches_in_one_graph": ms_loop_graph,
+        "ms_default_config_tau1": ms_default, "default_config": default_cfg,
+        "tuned_config": cfg, "tune_seconds": tune_s, "max_error_rate": args.max_error,
+        "threshold_histogram": hist, "error_rate_max": float(np.max(err)), "error_rate_mean": float(np.mean(err)),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "bytes_per_ray": total_bytes / n_rays},
+        "steps": args.steps, "timed_wall_s": wall,
+    }
 
 
 if __name__ == "__main__":

@@ -218,6 +218,95 @@ hyb_status hyb_df_backward(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float t
 hyb_status hyb_bvh_destroy(hyb_bvh bvh);
 hyb_status hyb_sdf_destroy(hyb_sdf sdf);
 
+/* ------------------------------------------------------------------------
+ * Batches: many scenes and ray sets of uneven size in one launch.
+ *
+ * Each item is an independent combined query (as hyb_trace) of its own scene
+ * with its own threshold; a batch runs all of them in one persistent kernel
+ * whose wavefronts take runs of rays_per_item rays of one item from a global
+ * work counter until every item is done.  hyb_batch_launch replays a HIP graph
+ * of two kernel nodes (a fill kernel that zeroes the counter, then the
+ * persistent trace); hyb_batch_launch_eager launches the same two kernels
+ * directly.  Results are bit-identical to hyb_trace per item, whatever the
+ * launch configuration.
+ *
+ * The batch keeps the item's pointers: the bvh, sdf, ray and hit buffers must
+ * stay valid until hyb_batch_destroy; new ray data may be written into the same
+ * buffers between launches.  All calls on one batch must be ordered (one
+ * stream, or synchronised by the caller): the batch's counter and descriptor
+ * table are shared by its launches.
+ * ------------------------------------------------------------------------ */
+typedef struct hyb_batch_s* hyb_batch;
+
+typedef struct {
+    hyb_bvh bvh;       /* may be NULL when threshold == 0 (distance field only) */
+    hyb_sdf sdf;       /* may be NULL when threshold == +inf (triangles only) */
+    hyb_rays rays;     /* device SoA, as for hyb_trace */
+    hyb_hits hits;     /* device SoA outputs, as for hyb_trace */
+    int64_t n;         /* rays of this item, >= 0 */
+    float tmax;        /* as for hyb_trace */
+    float threshold;   /* tau in voxels of this item's sdf, as for hyb_trace */
+} hyb_batch_item;
+
+/* Launch shape of the persistent kernel. */
+typedef struct {
+    int32_t lds_depth;      /* BVH stack entries per lane held in LDS: 8, 16 or 32 (rest spills) */
+    int32_t rays_per_item;  /* rays per work item, multiple of 64 in [64, 65536] */
+    int32_t blocks_per_cu;  /* 256-thread blocks per compute unit, 1..16 (capped by occupancy) */
+} hyb_batch_config;
+
+#define HYB_TUNE_THRESHOLD 1u /* choose each item's threshold */
+#define HYB_TUNE_LAUNCH 2u    /* choose the launch shape */
+
+typedef struct {
+    const float* thresholds; /* host, candidate thresholds (>= 0, +inf allowed); NULL: 0, 0.5, 1, 2, 4, +inf */
+    int32_t n_thresholds;    /* 0 with thresholds == NULL */
+    float max_error_rate;    /* per item: fraction of its rays allowed to differ from the triangles-only result */
+    int32_t reps;            /* timed launches per candidate, 1..100 */
+    uint32_t flags;          /* HYB_TUNE_THRESHOLD | HYB_TUNE_LAUNCH */
+} hyb_batch_tune_opts;
+
+/* Copies the items into a device descriptor table (synchronous on `stream`).
+ * Every item is validated as hyb_trace would; all sdfs of a batch must share
+ * one storage format (else HYB_ERR_UNSUPPORTED).  1 <= n_items <= 65536.
+ * Default config: lds_depth 16, rays_per_item 256, blocks_per_cu 4. */
+hyb_status hyb_batch_create(const hyb_batch_item* items, int32_t n_items, void* stream, hyb_batch* out);
+
+/* Configuration and per-item thresholds take effect at the next launch (which
+ * then re-uploads the table synchronously and, for hyb_batch_launch, rebuilds
+ * the graph when the launch shape changed).  set_threshold rejects a threshold
+ * an item cannot use (not 0 without a bvh, not +inf without an sdf). */
+hyb_status hyb_batch_set_config(hyb_batch batch, const hyb_batch_config* config);
+hyb_status hyb_batch_get_config(hyb_batch batch, hyb_batch_config* config);
+hyb_status hyb_batch_set_threshold(hyb_batch batch, int32_t item, float threshold);
+hyb_status hyb_batch_get_threshold(hyb_batch batch, int32_t item, float* threshold);
+
+/* Runs every item: one graph launch (asynchronous on `stream`). */
+hyb_status hyb_batch_launch(hyb_batch batch, void* stream);
+/* The same two kernels launched directly. */
+hyb_status hyb_batch_launch_eager(hyb_batch batch, void* stream);
+
+/* Autotuner (synchronous; overwrites the items' hit buffers).
+ * HYB_TUNE_THRESHOLD: for each item with both a bvh and an sdf and n > 0 (the
+ * others keep their threshold), traces its
+ * rays triangles-only as the reference, then at every candidate threshold;
+ * a ray counts as an error when hit/miss differs from the reference or both
+ * hit more than one voxel (h of the item's sdf) apart along the ray.  The item
+ * gets the candidate with the shortest measured time (fastest of `reps`
+ * single-item launches) among those with error rate <= max_error_rate, or
+ * +inf (exact) when none qualifies.
+ * HYB_TUNE_LAUNCH: times the whole batch (fastest of `reps` eager launches) for
+ * lds_depth {8,16,32} x rays_per_item {64,256,1024,4096} x blocks_per_cu
+ * {1,2,4,8} and keeps the fastest.
+ * item_error (host, n_items floats, may be NULL) receives each item's error
+ * rate at its chosen threshold (0 for items not tuned); best_ms (may be NULL)
+ * the fastest whole-batch time of the final configuration.  Allocates 16 bytes
+ * per ray of the largest item as scratch for the duration of the call. */
+hyb_status hyb_batch_tune(hyb_batch batch, const hyb_batch_tune_opts* opts, float* item_error, float* best_ms,
+                          void* stream);
+
+hyb_status hyb_batch_destroy(hyb_batch batch);
+
 /* Static string naming a status. */
 const char* hyb_status_str(hyb_status s);
 

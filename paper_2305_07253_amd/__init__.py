@@ -49,6 +49,23 @@ class _Hits(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("t", "prim", "u", "v")]
 
 
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("bvh", ctypes.c_void_p), ("sdf", ctypes.c_void_p), ("rays", _Rays), ("hits", _Hits),
+                ("n", ctypes.c_int64), ("tmax", ctypes.c_float), ("threshold", ctypes.c_float)]
+
+
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("lds_depth", ctypes.c_int32), ("rays_per_item", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
+class _TuneOpts(ctypes.Structure):
+    _fields_ = [("thresholds", ctypes.c_void_p), ("n_thresholds", ctypes.c_int32), ("max_error_rate", ctypes.c_float),
+                ("reps", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+TUNE_THRESHOLD, TUNE_LAUNCH = 1, 2
+
+
 _lib = None
 
 
@@ -77,6 +94,15 @@ def lib() -> ctypes.CDLL:
             "hyb_df_backward": [P, P, i64, f32, P, P, P, P],
             "hyb_bvh_destroy": [P],
             "hyb_sdf_destroy": [P],
+            "hyb_batch_create": [P, i32, P, PP],
+            "hyb_batch_set_config": [P, P],
+            "hyb_batch_get_config": [P, P],
+            "hyb_batch_set_threshold": [P, i32, f32],
+            "hyb_batch_get_threshold": [P, i32, P],
+            "hyb_batch_launch": [P, P],
+            "hyb_batch_launch_eager": [P, P],
+            "hyb_batch_tune": [P, P, P, P, P],
+            "hyb_batch_destroy": [P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -322,3 +348,81 @@ def trace_counters(bvh, sdf, rays, tmax: float, threshold: float, mode: int = MO
         None if bvh is None else bvh.handle, None if sdf is None else sdf.handle, ctypes.byref(r), n, tmax,
         threshold, mode, ctypes.byref(h), _ptr(counts), _stream(stream)))
     return out, counts
+
+
+class Batch:
+    """Many independent combined queries run by one persistent kernel (one HIP
+    graph launch).  `items` is a sequence of dicts with keys bvh, sdf, rays,
+    tmax, threshold and optionally out (hit buffers), tmin, tmax_ray; bvh may
+    be None for threshold 0, sdf None for threshold +inf.  The batch keeps
+    references to every tensor and handle it points at."""
+
+    def __init__(self, items, stream=None):
+        items = list(items)
+        arr = (_BatchItem * len(items))()
+        self._keep, self.outs = [], []
+        for k, it in enumerate(items):
+            thr = float(it["threshold"])
+            _query_args(float(it["tmax"]), thr)
+            r, n = _rays_struct(it["rays"], it.get("tmin"), it.get("tmax_ray"))
+            out = it.get("out") or alloc_hits(n)
+            arr[k].bvh = None if it.get("bvh") is None else it["bvh"].handle
+            arr[k].sdf = None if it.get("sdf") is None else it["sdf"].handle
+            arr[k].rays = r
+            arr[k].hits = _hits_struct(out, n)
+            arr[k].n = n
+            arr[k].tmax = float(it["tmax"])
+            arr[k].threshold = thr
+            self._keep.append((it.get("bvh"), it.get("sdf"), it["rays"], it.get("tmin"), it.get("tmax_ray"), out))
+            self.outs.append(out)
+        h = ctypes.c_void_p()
+        _check("hyb_batch_create", lib().hyb_batch_create(arr, len(items), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.n_items = len(items)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def launch(self, stream=None, graph: bool = True):
+        fn = "hyb_batch_launch" if graph else "hyb_batch_launch_eager"
+        _check(fn, getattr(lib(), fn)(self._h, _stream(stream)))
+        return self.outs
+
+    @property
+    def config(self):
+        c = _BatchConfig()
+        _check("hyb_batch_get_config", lib().hyb_batch_get_config(self._h, ctypes.byref(c)))
+        return dict(lds_depth=c.lds_depth, rays_per_item=c.rays_per_item, blocks_per_cu=c.blocks_per_cu)
+
+    @config.setter
+    def config(self, cfg):
+        c = _BatchConfig(int(cfg["lds_depth"]), int(cfg["rays_per_item"]), int(cfg["blocks_per_cu"]))
+        _check("hyb_batch_set_config", lib().hyb_batch_set_config(self._h, ctypes.byref(c)))
+
+    def threshold(self, item: int) -> float:
+        v = ctypes.c_float()
+        _check("hyb_batch_get_threshold", lib().hyb_batch_get_threshold(self._h, int(item), ctypes.byref(v)))
+        return v.value
+
+    def set_threshold(self, item: int, threshold: float):
+        _check("hyb_batch_set_threshold", lib().hyb_batch_set_threshold(self._h, int(item), float(threshold)))
+
+    def tune(self, max_error_rate: float, thresholds=None, reps: int = 3, threshold: bool = True,
+             launch: bool = True, stream=None):
+        """Autotune (synchronous; overwrites the hit buffers).  Returns
+        (per-item error rates at the chosen thresholds, fastest batch ms)."""
+        cands = None if thresholds is None else np.ascontiguousarray(thresholds, dtype=np.float32)
+        o = _TuneOpts(None if cands is None else cands.ctypes.data, 0 if cands is None else len(cands),
+                      float(max_error_rate), int(reps),
+                      (TUNE_THRESHOLD if threshold else 0) | (TUNE_LAUNCH if launch else 0))
+        err = np.zeros(self.n_items, dtype=np.float32)
+        ms = ctypes.c_float()
+        _check("hyb_batch_tune", lib().hyb_batch_tune(self._h, ctypes.byref(o), err.ctypes.data_as(ctypes.c_void_p),
+                                                      ctypes.byref(ms), _stream(stream)))
+        return err, ms.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hyb_batch_destroy(self._h)
+            self._h = None

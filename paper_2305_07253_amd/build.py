@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhyb.so")
 ARCH = os.environ.get("HYB_OFFLOAD_ARCH", "gfx950")
 
-HIP_SOURCES = ["trace.hip", "sdf.hip", "grad.hip", "api.hip"]
+HIP_SOURCES = ["trace.hip", "sdf.hip", "grad.hip", "batch.hip", "api.hip"]
 CXX_SOURCES = ["bvh_build.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = [

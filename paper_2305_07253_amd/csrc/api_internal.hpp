@@ -1,0 +1,143 @@
+// Internal to the C API: the handle structs behind include/hyb.h's opaque
+// handles and the argument helpers shared by the entry-point sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "hyb.h"
+#include "hyb_device.hpp"
+#include "kernels.hpp"
+
+struct hyb_bvh_s {
+    int device = 0;
+    float4* nodes = nullptr;
+    float4* tris = nullptr;
+    int64_t n_nodes = 0, n_tris = 0;
+    int32_t depth = 0;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+};
+
+struct hyb_sdf_s {
+    int device = 0;
+    float* values = nullptr;  // n^3 FP32 samples as the kernels see them (dequantized), x fastest
+    void* store = nullptr;    // F16 / I8 storage the kernels read (null for F32)
+    float* scales = nullptr;  // I8 block scales
+    int32_t n = 0, nb = 0;
+    float grid4[4] = {0, 0, 0, 0};
+    float lipschitz = 0.0f;
+    bool certified = false;  // samples are FP32 roundings of a 1-Lipschitz function
+    hyb_sdf_format fmt = HYB_SDF_F32;
+};
+
+namespace hyb_api {
+
+inline hyb_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return HYB_OK;
+    if (e == hipErrorOutOfMemory) return HYB_ERR_OOM;
+    return HYB_ERR_HIP;
+}
+
+#define HYB_TRY(expr)                               \
+    do {                                            \
+        hyb_status s_ = from_hip(expr);             \
+        if (s_ != HYB_OK) return s_;                \
+    } while (0)
+
+inline bool same_device(int dev) {
+    int cur = -1;
+    return hipGetDevice(&cur) == hipSuccess && cur == dev;
+}
+
+inline bool valid_rays(const hyb_rays* r) {
+    return r && r->ox && r->oy && r->oz && r->dx && r->dy && r->dz;
+}
+
+inline bool valid_hits(const hyb_hits* h) { return h && h->t && h->prim && h->u && h->v; }
+
+// Lipschitz bound of the stored grid: per-block maxima on the device, final
+// maximum on the host (build time; synchronous).
+inline hyb_status compute_lipschitz(hyb_sdf_s* s, hipStream_t stream) {
+    const int32_t nb = hyb::lipschitz_blocks(s->n);
+    float* d_blocks = nullptr;
+    HYB_TRY(hipMalloc(&d_blocks, sizeof(float) * nb));
+    int32_t got = 0;
+    hipError_t e = hyb::launch_lipschitz(s->values, s->n, s->grid4[3], d_blocks, &got, stream);
+    std::vector<float> host(nb, 0.0f);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), d_blocks, sizeof(float) * nb, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(d_blocks);
+    HYB_TRY(e);
+    float L = 0.0f;
+    for (float v : host) L = std::max(L, v);
+    if (!std::isfinite(L)) return HYB_ERR_INVALID_ARG;
+    s->lipschitz = hyb::finish_lipschitz(L);
+    return HYB_OK;
+}
+
+// Converts the FP32 samples in s->values to the handle's storage format; the
+// dequantized values replace s->values in place.
+inline hyb_status quantize(hyb_sdf_s* s, hipStream_t stream) {
+    if (s->fmt == HYB_SDF_F32) return HYB_OK;
+    const size_t count = static_cast<size_t>(s->n) * s->n * s->n;
+    s->nb = (s->n + hyb::kScaleBlock - 1) / hyb::kScaleBlock;
+    HYB_TRY(hipMalloc(&s->store, count * (s->fmt == HYB_SDF_F16 ? 2 : 1)));
+    if (s->fmt == HYB_SDF_I8_BRICK)
+        HYB_TRY(hipMalloc(&s->scales, sizeof(float) * static_cast<size_t>(s->nb) * s->nb * s->nb));
+    return from_hip(hyb::launch_quantize(s->fmt == HYB_SDF_F16 ? hyb::kF16 : hyb::kI8, s->values, s->n, s->store,
+                                         s->scales, s->values, stream));
+}
+
+inline bool valid_fmt(hyb_sdf_format f) { return f == HYB_SDF_F32 || f == HYB_SDF_F16 || f == HYB_SDF_I8_BRICK; }
+
+inline bool valid_grid4(const float* g) {
+    return g && std::isfinite(g[0]) && std::isfinite(g[1]) && std::isfinite(g[2]) && std::isfinite(g[3]) &&
+           g[3] > 0.0f;
+}
+
+inline void fill_trace_args(hyb::TraceArgs& a, const hyb_rays* rays, hyb_hits* hits, int64_t n, float tmax, float tau,
+                     float tau_end = 0.0f) {
+    std::memset(&a, 0, sizeof(a));
+    a.ox = rays->ox; a.oy = rays->oy; a.oz = rays->oz;
+    a.dx = rays->dx; a.dy = rays->dy; a.dz = rays->dz;
+    a.tmin = rays->tmin;
+    a.tmax_ray = rays->tmax;
+    a.tau_end = tau_end;
+    a.t = hits->t; a.prim = hits->prim; a.u = hits->u; a.v = hits->v;
+    a.tmax = tmax;
+    a.tau = tau;
+    a.n = n;
+}
+
+inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s) {
+    if (b) {
+        a.nodes = b->nodes;
+        a.tris = b->tris;
+    }
+    if (s) {
+        a.sdf = s->fmt == HYB_SDF_F32 ? static_cast<const void*>(s->values) : s->store;
+        a.scales = s->scales;
+        a.fmt = static_cast<int32_t>(s->fmt);
+        a.nb = s->nb;
+        a.n_grid = s->n;
+        a.lo_x = s->grid4[0];
+        a.lo_y = s->grid4[1];
+        a.lo_z = s->grid4[2];
+        a.h = s->grid4[3];
+        a.inv_h = 1.0f / s->grid4[3];
+        a.inv_l = hyb::inv_step(s->lipschitz);
+        a.two_e = (s->certified && s->fmt == HYB_SDF_F32) ? hyb::certified_slack(s->grid4[3], s->n) : __builtin_inff();
+    }
+}
+
+inline hyb_status check_query(const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits) {
+    if (n < 0 || std::isnan(tmax) || tmax < 0.0f) return HYB_ERR_INVALID_ARG;
+    if (n > 0 && (!valid_rays(rays) || !valid_hits(hits))) return HYB_ERR_INVALID_ARG;
+    return HYB_OK;
+}
+
+}  // namespace hyb_api

@@ -136,7 +136,7 @@ struct Hit {
 // ANY the traversal stops at the first intersection it finds (any-hit).
 // `stack` points at this lane's first LDS slot; consecutive entries are
 // `stride` ints apart (one slot per thread of the block, no bank conflicts).
-template <bool COUNT, bool ANY = false>
+template <bool COUNT, bool ANY = false, int LDS = kLdsDepth>
 HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                            float ox, float oy, float oz, float dx, float dy, float dz,
                                            float seg_lo, float seg_hi, int* stack, int stride, Counters& cnt) {
@@ -147,7 +147,8 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
     best.v = 0.0f;
     const BoxRay br = {ox, oy, oz, safe_inv(dx), safe_inv(dy), safe_inv(dz)};
     const ShearRay sr = make_shear(dx, dy, dz);
-    int spill[kStackDepth - kLdsDepth];
+    static_assert(LDS > 0 && LDS < kStackDepth, "LDS part of the stack out of range");
+    int spill[kStackDepth - LDS];
     int sp = 0;
     int ref = 0;  // root
     for (;;) {
@@ -164,8 +165,8 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
             if (h0 && h1) {
                 const bool first0 = tn0 <= tn1;
                 const int far = first0 ? r1 : r0;
-                if (sp < kLdsDepth) stack[sp * stride] = far;
-                else spill[sp - kLdsDepth] = far;
+                if (sp < LDS) stack[sp * stride] = far;
+                else spill[sp - LDS] = far;
                 ++sp;
                 ref = first0 ? r0 : r1;
                 continue;
@@ -194,7 +195,7 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
         }
         if (sp == 0) break;
         --sp;
-        ref = sp < kLdsDepth ? stack[sp * stride] : spill[sp - kLdsDepth];
+        ref = sp < LDS ? stack[sp * stride] : spill[sp - LDS];
     }
     if (best.prim < 0) best.t = __builtin_inff();
     return best;
@@ -584,7 +585,7 @@ inline float certified_slack(float h, int n) {
 }
 
 // One ray of a query (the body of the trace kernels).
-template <int MODE, int FMT, bool COUNT>
+template <int MODE, int FMT, bool COUNT, int LDS = kLdsDepth>
 HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
     const float ox = a.ox[i], oy = a.oy[i], oz = a.oz[i];
     const float dx = a.dx[i], dy = a.dy[i], dz = a.dz[i];
@@ -600,7 +601,7 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
         const Grid g = {a.sdf, a.scales, a.n_grid, a.nb, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e,
                         1.0 / (double)a.h};
         if (MODE == kBvhOnly) {
-            hit = bvh_closest<COUNT>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, tmax, stack, stride, cnt);
+            hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, tmax, stack, stride, cnt);
         } else if (MODE == kDfOnly) {
             const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, tmin, tmax, cnt);
             if (t < __builtin_inff()) {
@@ -621,15 +622,15 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
                 }
             }
             if (hit.prim == -1 && t1 > tmin)
-                hit = bvh_closest<COUNT, true>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt);
+                hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt);
             if (hit.prim == -1 && tmax > t2)
-                hit = bvh_closest<COUNT, true>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, t2, tmax, stack, stride, cnt);
+                hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, t2, tmax, stack, stride, cnt);
         } else {
             // Eq. (2) with two sub-queries processed in order (first hit):
             // triangles on [tmin, t1]; the distance field on [t1, tmax] only
             // when the first sub-query found nothing.
             const float t1 = fminf(fmaf(a.tau, a.h, tmin), tmax);
-            if (t1 > tmin) hit = bvh_closest<COUNT>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt);
+            if (t1 > tmin) hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt);
             if (hit.prim < 0 && (t1 < tmax || a.tau == 0.0f)) {
                 const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, tmax, cnt);
                 if (t < __builtin_inff()) {

@@ -32,6 +32,33 @@ struct TraceArgs {
 
 hipError_t launch_trace(int mode, bool counters, const TraceArgs& a, hipStream_t stream);
 
+// Persistent multi-scene trace (combined query of every scene).  Work item w
+// covers rays [(w - item_start[s]) * rays_per_item, ...) of the scene s with
+// item_start[s] <= w < item_start[s + 1]; wavefronts take items from the
+// global counter *queue (zero before the launch) until it passes n_items.
+struct BatchArgs {
+    const TraceArgs* scenes;     // device table, n_scenes entries
+    const uint32_t* item_start;  // device, n_scenes + 1 entries, item_start[n_scenes] = n_items
+    uint32_t* queue;             // device counter
+    int32_t n_scenes;
+    uint32_t n_items;
+    int32_t rays_per_item;       // multiple of 64
+};
+
+// Kernel entry of the persistent trace for a storage format and LDS stack
+// depth (8, 16 or 32 entries per lane), for launches and graph nodes; null
+// for an unsupported pair.  Its dynamic LDS is batch_lds_bytes(lds_depth).
+const void* batch_kernel(int fmt, int lds_depth);
+size_t batch_lds_bytes(int lds_depth);
+const void* queue_reset_kernel();  // one argument: uint32_t* counter, launch <<<1, 64>>>
+
+// Count of rays whose result differs from a reference result: hit/miss
+// differs, or both hit and the hit points are more than `h` apart
+// (|t - t_ref| |d| > h).  Adds the count to *count.
+hipError_t launch_count_mismatch(const float* t, const int32_t* prim, const float* t_ref, const int32_t* prim_ref,
+                                 const float* dx, const float* dy, const float* dz, int64_t n, float h,
+                                 unsigned long long* count, hipStream_t stream);
+
 // Storage conversion of an n^3 FP32 grid (x fastest).
 //   F16: out16[i] = round-to-nearest-even half of in[i]
 //   I8:  scales[b] = max |in| over the nodes of 8^3 block b / 127 (1 if that is 0),

@@ -574,3 +574,52 @@ def rebias(rays: Rays, gb: GBuffer, eps: float, spp: int = 1) -> Rays:
     p = np.repeat(gb.p, spp, axis=0)
     n = np.repeat(gb.n, spp, axis=0)
     return Rays((p + eps * n).astype(np.float32), rays.d.copy())
+
+
+# ----------------------------------------------------------------------------
+# many scenes of uneven size (batched tracing)
+# ----------------------------------------------------------------------------
+
+TRIS_PER_OBJECT = 376  # mean of the 432-triangle boxes and 320-triangle icospheres
+
+
+@dataclasses.dataclass
+class BatchSceneSpec:
+    seed: int
+    n_objects: int
+    s_min: float
+    s_max: float
+    n_grid: int
+    width: int
+    height: int
+
+    @property
+    def n_rays(self) -> int:
+        return self.width * self.height
+
+
+def batch_specs(seed: int = 4, n_scenes: int = 64, tris=(1e3, 5e5), rays=(1e3, 2e6)) -> list:
+    """Scenes of log-uniform size in `tris` triangles, each with a log-uniform
+    number of rays in `rays` (one diffuse ray per pixel of a 16:9 G-buffer
+    whose sides are multiples of 8) and a grid of 32^3 at the smallest size
+    to 128^3 at the largest, log-linear in the triangle count (multiples of 8).
+    Object sizes grow as objects get fewer, so every scene fills the room
+    about as densely as the GI-shaped scene."""
+    rng = _rng(seed)
+    out = []
+    lt, lr = np.log(tris), np.log(rays)
+    for s in range(n_scenes):
+        t = math.exp(rng.uniform(lt[0], lt[1]))
+        r = math.exp(rng.uniform(lr[0], lr[1]))
+        n_obj = max(2, int(round((t - 12) / TRIS_PER_OBJECT)))
+        s_max = min(0.25, 0.06 * (500.0 / n_obj) ** (1.0 / 3.0))
+        frac = (math.log(t) - lt[0]) / (lt[1] - lt[0])
+        n_grid = int(min(128, max(32, 8 * round(32 * 4.0 ** frac / 8))))
+        w = max(8, 8 * int(round(math.sqrt(r * 16.0 / 9.0) / 8)))
+        h = max(8, 8 * int(round(r / w / 8)))
+        out.append(BatchSceneSpec(1000 * seed + s, n_obj, s_max / 10.0, s_max, n_grid, w, h))
+    return out
+
+
+def batch_scene(spec: BatchSceneSpec) -> Scene:
+    return make_scene(spec.seed, spec.n_objects, spec.s_min, spec.s_max)

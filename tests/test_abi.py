@@ -74,3 +74,49 @@ def test_python_binding_validates(lib):
         hyb._query_args(1.0, -1.0)
     with pytest.raises(hyb.HybError):
         hyb.build_bvh(np.array([[0, 0, 0]], np.float32), np.array([[0, 0, 5]], np.int32))
+
+
+def test_batch_arguments_rejected_before_device_work(lib):
+    import paper_2305_07253_amd as hyb
+    P = ctypes.c_void_p
+    out = P()
+    items = (hyb._BatchItem * 2)()
+    assert lib.hyb_batch_create(None, 1, None, ctypes.byref(out)) == 1
+    assert lib.hyb_batch_create(items, 0, None, ctypes.byref(out)) == 1
+    assert lib.hyb_batch_create(items, 1 << 17, None, ctypes.byref(out)) == 1
+    assert lib.hyb_batch_create(items, 1, None, None) == 1
+    assert lib.hyb_batch_create(items, 2, None, ctypes.byref(out)) == 1  # neither bvh nor sdf
+    cfg = hyb._BatchConfig(16, 256, 4)
+    assert lib.hyb_batch_set_config(None, ctypes.byref(cfg)) == 1
+    assert lib.hyb_batch_get_config(None, ctypes.byref(cfg)) == 1
+    assert lib.hyb_batch_set_threshold(None, 0, 1.0) == 1
+    assert lib.hyb_batch_get_threshold(None, 0, None) == 1
+    assert lib.hyb_batch_launch(None, None) == 1
+    assert lib.hyb_batch_launch_eager(None, None) == 1
+    opts = hyb._TuneOpts(None, 0, 0.01, 3, 3)
+    assert lib.hyb_batch_tune(None, ctypes.byref(opts), None, None, None) == 1
+    assert lib.hyb_batch_destroy(None) == 1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes
+    and field offsets."""
+    import subprocess
+    import paper_2305_07253_amd as hyb
+    mirrors = {"hyb_rays": hyb._Rays, "hyb_hits": hyb._Hits, "hyb_batch_item": hyb._BatchItem,
+               "hyb_batch_config": hyb._BatchConfig, "hyb_batch_tune_opts": hyb._TuneOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hyb.h"', "int main(void) {"]
+    for c, m in mirrors.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (c, c))
+        for f, _ in m._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (c, f, c, f))
+    lines.append("return 0; }")
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text("\n".join(lines))
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], stdout=subprocess.PIPE, text=True,
+                                                 check=True).stdout.splitlines())
+    for c, m in mirrors.items():
+        assert int(got[c]) == ctypes.sizeof(m), c
+        for f, _ in m._fields_:
+            assert int(got["%s.%s" % (c, f)]) == getattr(m, f).offset, (c, f)
