@@ -59,7 +59,11 @@ typedef struct hyb_sdf_s* hyb_sdf; /* distance-field grid; library-owned device 
  *                     scale = max |f| over the block / 127 (1 if that is 0),
  *                     q = rint(f / scale) clamped to [-127, 127] (FP32 division,
  *                     round half to even), value = q * scale (FP32).
- * Compact formats do not use the certified-sample step bound. */
+ * Compact formats do not use the certified-sample step bound.  Inside the
+ * library the samples the kernels read are laid out in 4x4x4-node bricks
+ * (cache-line-compact blocks of nodes); every interface that takes or returns
+ * grid values (hyb_sdf_from_grid, hyb_sdf_read, hyb_df_backward) uses the
+ * linear n^3 order, x fastest. */
 typedef enum {
     HYB_SDF_F32 = 0,
     HYB_SDF_F16 = 1,

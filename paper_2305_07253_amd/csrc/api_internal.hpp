@@ -25,7 +25,7 @@ struct hyb_bvh_s {
 struct hyb_sdf_s {
     int device = 0;
     float* values = nullptr;  // n^3 FP32 samples as the kernels see them (dequantized), x fastest
-    void* store = nullptr;    // F16 / I8 storage the kernels read (null for F32)
+    void* store = nullptr;    // the samples the kernels read: storage format, bricked layout
     float* scales = nullptr;  // I8 block scales
     int32_t n = 0, nb = 0;
     float grid4[4] = {0, 0, 0, 0};
@@ -79,17 +79,18 @@ inline hyb_status compute_lipschitz(hyb_sdf_s* s, hipStream_t stream) {
     return HYB_OK;
 }
 
-// Converts the FP32 samples in s->values to the handle's storage format; the
-// dequantized values replace s->values in place.
+// Writes the kernels' copy of the FP32 samples in s->values (storage format,
+// bricked layout); for the compact formats the dequantized values replace
+// s->values in place.
 inline hyb_status quantize(hyb_sdf_s* s, hipStream_t stream) {
-    if (s->fmt == HYB_SDF_F32) return HYB_OK;
-    const size_t count = static_cast<size_t>(s->n) * s->n * s->n;
+    const int fmt = s->fmt == HYB_SDF_F32 ? hyb::kF32 : (s->fmt == HYB_SDF_F16 ? hyb::kF16 : hyb::kI8);
+    const size_t count = static_cast<size_t>(hyb::brick_storage(fmt, s->n));
+    const size_t elem = s->fmt == HYB_SDF_F32 ? 4 : (s->fmt == HYB_SDF_F16 ? 2 : 1);
     s->nb = (s->n + hyb::kScaleBlock - 1) / hyb::kScaleBlock;
-    HYB_TRY(hipMalloc(&s->store, count * (s->fmt == HYB_SDF_F16 ? 2 : 1)));
+    HYB_TRY(hipMalloc(&s->store, count * elem));
     if (s->fmt == HYB_SDF_I8_BRICK)
         HYB_TRY(hipMalloc(&s->scales, sizeof(float) * static_cast<size_t>(s->nb) * s->nb * s->nb));
-    return from_hip(hyb::launch_quantize(s->fmt == HYB_SDF_F16 ? hyb::kF16 : hyb::kI8, s->values, s->n, s->store,
-                                         s->scales, s->values, stream));
+    return from_hip(hyb::launch_quantize(fmt, s->values, s->n, s->store, s->scales, stream));
 }
 
 inline bool valid_fmt(hyb_sdf_format f) { return f == HYB_SDF_F32 || f == HYB_SDF_F16 || f == HYB_SDF_I8_BRICK; }
@@ -119,7 +120,7 @@ inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s
         a.tris = b->tris;
     }
     if (s) {
-        a.sdf = s->fmt == HYB_SDF_F32 ? static_cast<const void*>(s->values) : s->store;
+        a.sdf = s->store;
         a.scales = s->scales;
         a.fmt = static_cast<int32_t>(s->fmt);
         a.nb = s->nb;

@@ -209,7 +209,7 @@ enum SdfFormat : int { kF32 = 0, kF16 = 1, kI8 = 2 };
 constexpr int kScaleBlock = 8;  // I8: one scale per 8^3 block of nodes
 
 struct Grid {
-    const void* __restrict__ v;        // n^3 samples, x fastest (float, _Float16 or int8_t)
+    const void* __restrict__ v;        // samples in the bricked layout Brick<FMT> (float, _Float16 or int8_t)
     const float* __restrict__ scales;  // I8: per node block (node (i,j,k) -> block (i/8, j/8, k/8))
     int n, nb;                         // samples per axis, scale blocks per axis
     float lo_x, lo_y, lo_z, h, inv_h;
@@ -220,26 +220,78 @@ struct Grid {
 
 // The 8 corner samples of cell (i, j, k), dequantized to FP32:
 // f[dx + 2 dy + 4 dz] = sample(i + dx, j + dy, k + dz).
+// Kernel-side layout of the samples: the cells are grouped into bricks of
+// C^3 cells, and each brick stores all (C + 1)^3 nodes of its cells (the faces
+// it shares with neighbouring bricks are duplicated), x fastest inside a
+// brick, bricks x fastest.  The 8 corners of any cell then lie in one brick at
+// fixed offsets from one address: a fetch is a few wide loads with immediate
+// offsets inside one or two cache lines, and the nodes around a ray share
+// lines.  C per format (fastest measured on the GI-shaped workload):
+//   F32: C = 2, 27 samples per 8 cells (3.4x the n^3 samples), a fetch spans 56 B
+//   F16, I8: C = 1, the 8 corners of each cell contiguous (16 / 8 B, one load)
+// Slots of nodes beyond the grid are padding and never read.
+template <int FMT>
+struct Brick {
+    static constexpr int kCells = FMT == kF32 ? 2 : 1;
+    static constexpr int kSide = kCells + 1;
+    static constexpr int kNodes = kSide * kSide * kSide;
+
+    HYB_HD static int per_axis(int n) { return (n - 1 + kCells - 1) / kCells; }
+
+    HYB_HD static int64_t storage(int n) {
+        const int64_t b = per_axis(n);
+        return b * b * b * kNodes;
+    }
+
+    // Storage slot of corner 0 (the node (i, j, k)) of cell (i, j, k).
+    HYB_HD static int64_t cell_slot(int i, int j, int k, int nbk) {
+        const int bi = i / kCells, bj = j / kCells, bk = k / kCells;
+        const int r = (i - bi * kCells) + kSide * ((j - bj * kCells) + kSide * (k - bk * kCells));
+        return (((int64_t)bk * nbk + bj) * nbk + bi) * kNodes + r;
+    }
+
+    // The node stored in slot s; false for a padding slot.
+    HYB_HD static bool slot_node(int64_t s, int n, int& i, int& j, int& k) {
+        const int nbk = per_axis(n);
+        const int64_t b = s / kNodes;
+        const int r = (int)(s - b * kNodes);
+        const int bi = (int)(b % nbk), bj = (int)((b / nbk) % nbk), bk = (int)(b / ((int64_t)nbk * nbk));
+        i = bi * kCells + r % kSide;
+        j = bj * kCells + (r / kSide) % kSide;
+        k = bk * kCells + r / (kSide * kSide);
+        return i < n && j < n && k < n;
+    }
+};
+
+// Slots of the bricked storage of an n^3 grid in format fmt (runtime format).
+inline int64_t brick_storage(int fmt, int n) {
+    return fmt == kF32 ? Brick<kF32>::storage(n) : (fmt == kF16 ? Brick<kF16>::storage(n) : Brick<kI8>::storage(n));
+}
+
+// The 8 samples of cell (i, j, k), corner c = (i + (c & 1), j + (c >> 1 & 1), k + (c >> 2)).
 template <int FMT>
 HYB_HD void corners(const Grid& g, int i, int j, int k, float f[8]) {
-    const int64_t n = g.n;
-    const int64_t base = (int64_t)i + n * ((int64_t)j + n * (int64_t)k);
-    const int64_t off[8] = {0, 1, n, n + 1, n * n, n * n + 1, n * n + n, n * n + n + 1};
+    using B = Brick<FMT>;
+    constexpr int S = B::kSide, S2 = B::kSide * B::kSide;
+    constexpr int off[8] = {0, 1, S, S + 1, S2, S2 + 1, S2 + S, S2 + S + 1};
+    const int64_t slot = B::cell_slot(i, j, k, B::per_axis(g.n));
     if constexpr (FMT == kF32) {
-        const float* p = static_cast<const float*>(g.v) + base;
+        const float* p = static_cast<const float*>(g.v) + slot;
         for (int c = 0; c < 8; ++c) f[c] = p[off[c]];
     } else if constexpr (FMT == kF16) {
-        const _Float16* p = static_cast<const _Float16*>(g.v) + base;
+        const _Float16* p = static_cast<const _Float16*>(g.v) + slot;
         for (int c = 0; c < 8; ++c) f[c] = (float)p[off[c]];
     } else {
-        const int8_t* p = static_cast<const int8_t*>(g.v) + base;
-        const int bi0 = i / kScaleBlock, bi1 = (i + 1) / kScaleBlock;
-        const int bj0 = j / kScaleBlock, bj1 = (j + 1) / kScaleBlock;
-        const int bk0 = k / kScaleBlock, bk1 = (k + 1) / kScaleBlock;
-        const int nb = g.nb;
+        const int8_t* p = static_cast<const int8_t*>(g.v) + slot;
+        const uint32_t nb = (uint32_t)g.nb;
+        const uint32_t bi0 = (uint32_t)i / kScaleBlock, bi1 = (uint32_t)(i + 1) / kScaleBlock;
+        const uint32_t bj0 = (uint32_t)j / kScaleBlock, bj1 = (uint32_t)(j + 1) / kScaleBlock;
+        const uint32_t bk0 = (uint32_t)k / kScaleBlock, bk1 = (uint32_t)(k + 1) / kScaleBlock;
+        const char* sp = reinterpret_cast<const char*>(g.scales);
         for (int c = 0; c < 8; ++c) {
-            const int bi = (c & 1) ? bi1 : bi0, bj = (c & 2) ? bj1 : bj0, bk = (c & 4) ? bk1 : bk0;
-            f[c] = (float)p[off[c]] * g.scales[bi + nb * (bj + nb * bk)];
+            const uint32_t bi = (c & 1) ? bi1 : bi0, bj = (c & 2) ? bj1 : bj0, bk = (c & 4) ? bk1 : bk0;
+            const float scale = *reinterpret_cast<const float*>(sp + ((bi + nb * (bj + nb * bk)) << 2));
+            f[c] = (float)p[off[c]] * scale;
         }
     }
 }

@@ -59,13 +59,16 @@ hipError_t launch_count_mismatch(const float* t, const int32_t* prim, const floa
                                  const float* dx, const float* dy, const float* dz, int64_t n, float h,
                                  unsigned long long* count, hipStream_t stream);
 
-// Storage conversion of an n^3 FP32 grid (x fastest).
-//   F16: out16[i] = round-to-nearest-even half of in[i]
-//   I8:  scales[b] = max |in| over the nodes of 8^3 block b / 127 (1 if that is 0),
-//        out8[i] = rint(in[i] / scale of its block) clamped to [-127, 127]
-// deq receives the dequantized FP32 values (what the trace kernels see).
-hipError_t launch_quantize(int fmt, const float* in, int32_t n, void* out, float* scales, float* deq,
-                           hipStream_t stream);
+// The kernels' copy of an n^3 FP32 grid (x fastest): `out` receives
+// brick_storage(fmt, n) samples in the format's bricked layout (slot s holds
+// the node Brick<fmt>::slot_node(s)), in the storage format:
+//   F32: the value
+//   F16: round-to-nearest-even half of the value
+//   I8:  scales[b] = max |value| over the nodes of 8^3 block b / 127 (1 if that
+//        is 0), q = rint(value / scale of its block) clamped to [-127, 127]
+// For F16 / I8, `values` is then overwritten in place by the dequantized FP32
+// values (what the trace kernels interpolate).
+hipError_t launch_quantize(int fmt, float* values, int32_t n, void* out, float* scales, hipStream_t stream);
 
 // Scatter of d loss / d grid sample for distance-field hits (hyb_df_backward).
 hipError_t launch_df_backward(const TraceArgs& a, const float* t_hit, const float* grad_t, float* grad_grid,

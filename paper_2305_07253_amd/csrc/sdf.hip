@@ -55,40 +55,66 @@ __global__ __launch_bounds__(256) void k_block_scales(const float* __restrict__ 
 }
 
 // Per-node conversion to F16 or I8 and the dequantized FP32 value.
+// One storage slot of the bricked layout: the sample of its node in the
+// storage format (0 for padding slots).
 template <int FMT>
-__global__ __launch_bounds__(256) void k_quantize(const float* __restrict__ in, int32_t n, int32_t nb, void* out,
-                                                  const float* __restrict__ scales, float* __restrict__ deq) {
+__global__ __launch_bounds__(256) void k_store(const float* __restrict__ in, int32_t n, int32_t nb, int64_t slots,
+                                               void* __restrict__ out, const float* __restrict__ scales) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= slots) return;
+    int i, j, k;
+    const bool node = Brick<FMT>::slot_node(s, n, i, j, k);
+    const float f = node ? in[(int64_t)i + (int64_t)n * ((int64_t)j + (int64_t)n * k)] : 0.0f;
+    if constexpr (FMT == kF32) {
+        static_cast<float*>(out)[s] = f;
+    } else if constexpr (FMT == kF16) {
+        static_cast<_Float16*>(out)[s] = (_Float16)f;
+    } else {
+        float q = 0.0f;
+        if (node) {
+            const float sc = scales[i / kScaleBlock + nb * (j / kScaleBlock + nb * (k / kScaleBlock))];
+            q = fminf(fmaxf(rintf(f / sc), -127.0f), 127.0f);
+        }
+        static_cast<int8_t*>(out)[s] = (int8_t)q;
+    }
+}
+
+// The dequantized FP32 value of every node, in place (linear order).
+template <int FMT>
+__global__ __launch_bounds__(256) void k_dequantize(float* __restrict__ values, int32_t n, int32_t nb,
+                                                    const float* __restrict__ scales) {
     const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t nn = (int64_t)n;
     if (id >= nn * nn * nn) return;
-    const float f = in[id];
+    const float f = values[id];
     if constexpr (FMT == kF16) {
-        const _Float16 q = (_Float16)f;
-        static_cast<_Float16*>(out)[id] = q;
-        deq[id] = (float)q;
+        values[id] = (float)(_Float16)f;
     } else {
         const int i = (int)(id % nn), j = (int)((id / nn) % nn), k = (int)(id / (nn * nn));
-        const float s = scales[i / kScaleBlock + nb * (j / kScaleBlock + nb * (k / kScaleBlock))];
-        const float q = fminf(fmaxf(rintf(f / s), -127.0f), 127.0f);
-        static_cast<int8_t*>(out)[id] = (int8_t)q;
-        deq[id] = q * s;
+        const float sc = scales[i / kScaleBlock + nb * (j / kScaleBlock + nb * (k / kScaleBlock))];
+        values[id] = fminf(fmaxf(rintf(f / sc), -127.0f), 127.0f) * sc;
     }
 }
 
 }  // namespace
 
-hipError_t launch_quantize(int fmt, const float* in, int32_t n, void* out, float* scales, float* deq,
-                           hipStream_t stream) {
+hipError_t launch_quantize(int fmt, float* values, int32_t n, void* out, float* scales, hipStream_t stream) {
     const int64_t total = (int64_t)n * n * n;
     const unsigned blocks = (unsigned)((total + 255) / 256);
+    const int64_t slots = brick_storage(fmt, n);
+    const unsigned sblocks = (unsigned)((slots + 255) / 256);
     const int32_t nb = (n + kScaleBlock - 1) / kScaleBlock;
-    if (fmt == kF16) {
-        hipLaunchKernelGGL(k_quantize<kF16>, dim3(blocks), dim3(256), 0, stream, in, n, nb, out, scales, deq);
+    if (fmt == kF32) {
+        hipLaunchKernelGGL(k_store<kF32>, dim3(sblocks), dim3(256), 0, stream, values, n, nb, slots, out, scales);
+    } else if (fmt == kF16) {
+        hipLaunchKernelGGL(k_store<kF16>, dim3(sblocks), dim3(256), 0, stream, values, n, nb, slots, out, scales);
+        hipLaunchKernelGGL(k_dequantize<kF16>, dim3(blocks), dim3(256), 0, stream, values, n, nb, scales);
     } else if (fmt == kI8) {
         const int64_t nbb = (int64_t)nb * nb * nb;
-        hipLaunchKernelGGL(k_block_scales, dim3((unsigned)((nbb + 255) / 256)), dim3(256), 0, stream, in, n, nb,
+        hipLaunchKernelGGL(k_block_scales, dim3((unsigned)((nbb + 255) / 256)), dim3(256), 0, stream, values, n, nb,
                            scales);
-        hipLaunchKernelGGL(k_quantize<kI8>, dim3(blocks), dim3(256), 0, stream, in, n, nb, out, scales, deq);
+        hipLaunchKernelGGL(k_store<kI8>, dim3(sblocks), dim3(256), 0, stream, values, n, nb, slots, out, scales);
+        hipLaunchKernelGGL(k_dequantize<kI8>, dim3(blocks), dim3(256), 0, stream, values, n, nb, scales);
     } else {
         return hipErrorInvalidValue;
     }

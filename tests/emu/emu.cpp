@@ -11,6 +11,7 @@
 //         verts f32[3 n_verts], tris i32[3 n_tris],
 //         grid (what 0, N > 0): f32[N^3] dequantized values, then the stored
 //           values (f16 or i8 [N^3]) and f32 block scales [nb^3] for fmt 1/2,
+//           all x fastest (the emulator lays them out in bricks),
 //         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays], tmax f32[n_rays]
 // what 0 (trace): output t f32[n], prim i32[n], u f32[n], v f32[n], counts i32[3n]
 // what 1 (sdf):   output f32[N^3] signed distances of the grid nodes
@@ -94,6 +95,23 @@ int main(int argc, char** argv) {
             }
     L = hyb::finish_lipschitz(L);
 
+    // the kernels read the samples in the format's bricked layout (exact-size
+    // buffers, so the sanitizer sees any read past the storage); the FP32
+    // copy also serves the backward body
+    const size_t n32 = N > 0 ? (size_t)hyb::Brick<hyb::kF32>::storage((int)N) : 0;
+    const size_t n16 = N > 0 ? (size_t)hyb::Brick<hyb::kF16>::storage((int)N) : 0;
+    const size_t n8 = N > 0 ? (size_t)hyb::Brick<hyb::kI8>::storage((int)N) : 0;
+    std::vector<float> b32(grid.empty() ? 0 : n32, 0.0f);
+    std::vector<_Float16> b16(g16.empty() ? 0 : n16, (_Float16)0.0f);
+    std::vector<int8_t> b8(g8.empty() ? 0 : n8, 0);
+    int i, j, k;
+    for (size_t s = 0; s < b32.size(); ++s)
+        if (hyb::Brick<hyb::kF32>::slot_node((int64_t)s, (int)N, i, j, k)) b32[s] = grid.at(i + N * (j + N * (long long)k));
+    for (size_t s = 0; s < b16.size(); ++s)
+        if (hyb::Brick<hyb::kF16>::slot_node((int64_t)s, (int)N, i, j, k)) b16[s] = g16.at(i + N * (j + N * (long long)k));
+    for (size_t s = 0; s < b8.size(); ++s)
+        if (hyb::Brick<hyb::kI8>::slot_node((int64_t)s, (int)N, i, j, k)) b8[s] = g8.at(i + N * (j + N * (long long)k));
+
     std::vector<float> t(n), u(n), v(n);
     std::vector<int32_t> prim(n), counts(3 * n);
     hyb::TraceArgs a{};
@@ -106,8 +124,8 @@ int main(int argc, char** argv) {
     a.nodes = nodes.data();
     a.tris = tri4.data();
     a.sdf = grid.empty() ? nullptr
-            : (fmt == 1 ? static_cast<const void*>(g16.data())
-                        : (fmt == 2 ? static_cast<const void*>(g8.data()) : static_cast<const void*>(grid.data())));
+            : (fmt == 1 ? static_cast<const void*>(b16.data())
+                        : (fmt == 2 ? static_cast<const void*>(b8.data()) : static_cast<const void*>(b32.data())));
     a.scales = scales.empty() ? nullptr : scales.data();
     a.fmt = fmt;
     a.nb = (int)nb;
@@ -119,7 +137,7 @@ int main(int argc, char** argv) {
     a.tau = par[1];
     a.n = n;
     if (what == 2) {
-        const hyb::Grid g = {grid.data(), nullptr, (int)N, 0, par[2], par[3], par[4], par[5], inv_h, a.inv_l,
+        const hyb::Grid g = {b32.data(), nullptr, (int)N, 0, par[2], par[3], par[4], par[5], inv_h, a.inv_l,
                              __builtin_inff(), 1.0 / (double)par[5]};
         std::vector<long long> nodes(8 * n, -1);
         std::vector<float> dts(8 * n, 0.0f);

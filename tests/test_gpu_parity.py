@@ -388,3 +388,23 @@ def test_autograd_df_hit(hyb, tiny):
     ref = torch.zeros(32 ** 3, device="cuda")
     hyb.df_backward(sdf, R, 2.0, t2, torch.where(torch.isfinite(t2), w, torch.zeros_like(w)).contiguous(), ref)
     assert torch.allclose(theta.grad.reshape(-1), ref, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("n", [30, 33, 35])
+def test_grid_sizes_with_partial_bricks(hyb, orc, tiny, tiny_dev, n):
+    """Grid sides that are not a multiple of the 4-node brick or the 8-node
+    I8 scale block, every storage format, against the oracle."""
+    from paper_2305_07253_amd import workloads as W
+    sc = tiny["scene"]
+    g4 = W.room_grid(n)
+    grid = orc.sdf_grid(sc, g4, n)
+    s = tiny["free"].soa()
+    for fmt in (0, 1, 2):
+        sdf = hyb.sdf_from_grid(to_dev(grid.reshape(-1)), g4, fmt=fmt)
+        deq = orc.quantize(grid, fmt)[0] if fmt else grid
+        assert np.array_equal(hyb.sdf_read(sdf).cpu().numpy(), np.asarray(deq, np.float32).reshape(n, n, n))
+        for tau in (0.0, 1.0):
+            got = host(hyb.trace(tiny_dev["bvh"], sdf, tiny_dev["free"], 2.0, tau))
+            ref = orc.query(sc.verts, sc.tris, deq, g4, s, 2.0, tau)
+            m, c = orc.margin(sc.verts, sc.tris, deq, g4, s, 2.0, tau)
+            parity.check(got, ref, m, c, label="gpu n=%d fmt %d tau %s" % (n, fmt, tau))

@@ -162,3 +162,21 @@ def test_df_gradient_matches_oracle(emu, orc, tiny):
     assert np.all(np.abs(dt[ok] - rdt[ok]) <= 1e-4 * np.maximum(np.abs(rdt[ok]).max(axis=1, keepdims=True), 1.0))
     # rays whose hit is the start of their segment contribute nothing on either side
     assert np.array_equal(nodes[:, 0] == -1, rn[:, 0] == -1)
+
+
+@pytest.mark.parametrize("n", [30, 33, 35])
+def test_grid_sizes_with_partial_bricks(emu, orc, tiny, n):
+    """Grids whose side is not a multiple of the 4-node brick (and, for I8, of
+    the 8-node scale block): every format against the oracle."""
+    from paper_2305_07253_amd import workloads as W
+    sc = tiny["scene"]
+    g4 = W.room_grid(n)
+    grid = orc.sdf_grid(sc, g4, n)
+    rays = tiny["free"].soa()[:, :1024]
+    for fmt in (0, 1, 2):
+        deq = orc.quantize(grid, fmt)[0] if fmt else grid
+        for tau in (0.0, 1.0):
+            got = emu.trace(sc.verts, sc.tris, grid, g4, rays, 2.0, tau, fmt=fmt)
+            ref = orc.query(sc.verts, sc.tris, deq, g4, rays, 2.0, tau)
+            m, c = orc.margin(sc.verts, sc.tris, deq, g4, rays, 2.0, tau)
+            parity.check(got, ref, m, c, label="emu n=%d fmt %d tau %s" % (n, fmt, tau))
