@@ -246,8 +246,12 @@ def main():
             m = int(min(n, max(2 * m, m * 15.0 / max(el, 1e-3))))
         cpu = dict(value=sub.n / el / 1e6, unit="Mrays/s", cores=oracle.threads(), kind="oracle",
                    sample="%d of the %d rays at a fixed stride over the tile-ordered G-buffer rays (%.1f s), "
-                          "combined query at threshold %s, brute force over all %d triangles, FP64" % (
-                              sub.n, n, el, chosen["tau"], scene.n_tris))
+                          "combined query at threshold %s in FP64: %s" % (
+                              sub.n, n, el, chosen["tau"],
+                              "distance field only (the triangle segment is empty at threshold 0), cell-by-cell "
+                              "walk with exact per-cell roots" if tau == 0 else
+                              "brute force over all %d triangles on the triangle segment, cell-by-cell walk with "
+                              "exact per-cell roots on the distance-field segment" % scene.n_tris))
         log("cpu oracle: %.4f Mrays/s (%.1fs, %d threads)" % (cpu["value"], el, cpu["cores"]))
 
     line = {
