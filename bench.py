@@ -299,6 +299,8 @@ def run_extra(args):
         line = bench_precision(args, torch, hyb, W, dev, stream)
     elif args.config == "batch":
         line = bench_batch(args, torch, hyb, W, dev, stream)
+    elif args.config == "shadow":
+        line = bench_shadow(args, torch, hyb, W, dev, stream)
     else:
         raise SystemExit("config %s not implemented" % args.config)
     print(json.dumps(line), flush=True)
@@ -560,6 +562,47 @@ def bench_batch(args, torch, hyb, W, dev, stream):
                      "frac": achieved / HBM_PEAK_GBS, "bytes_per_ray": total_bytes / n_rays},
         "steps": args.steps, "timed_wall_s": wall,
     }
+
+
+
+def bench_shadow(args, torch, hyb, W, dev, stream):
+    """The shadow-ray query on the GI-shaped scene: one ray per G-buffer pixel
+    to a uniform sample of the area light, thresholds swept at both ends,
+    against the exact any-hit triangle query (both thresholds +inf)."""
+    t0 = time.time()
+    scene = W.gi_scene(2)
+    gb = W.gbuffer(scene, args.width, args.height)
+    srays, stmax = W.shadow_rays(gb.p, gb.n, 22)
+    n = srays.n
+    bvh = hyb.build_bvh(scene.verts, scene.tris)
+    g4 = W.room_grid(128)
+    sdf = hyb.build_sdf(bvh, 128, g4)
+    R, TS = torch.from_numpy(srays.soa()).to(dev), torch.from_numpy(stmax).to(dev)
+    out = hyb.alloc_hits(n)
+    log("shadow workload: %d triangles, %d rays (%.1fs)" % (scene.n_tris, n, time.time() - t0))
+    big = 10.0  # every ray ends at its light sample (per-ray tmax)
+
+    def run(ts, te):
+        return lambda: hyb.trace_shadow(bvh, sdf, R, big, ts, te, tmax_ray=TS, out=out)
+
+    ms_ref = time_launches(run(math.inf, math.inf), stream, args.reps, 2)
+    ref = out[1].cpu().numpy() != -1
+    res = []
+    for ts, te in ((0.0, 0.0), (0.5, 0.5), (1.0, 1.0), (2.0, 2.0), (4.0, 4.0), (1.0, 4.0)):
+        ms = time_launches(run(ts, te), stream, args.reps, 2)
+        occ = out[1].cpu().numpy() != -1
+        res.append(dict(threshold_start=ts, threshold_end=te, ms=ms, mrays_s=n / ms / 1e3,
+                        occlusion_mismatch=float((occ != ref).mean()), false_occlusion=float((occ & ~ref).mean()),
+                        missed_occlusion=float((~occ & ref).mean()), df_occluded=float((out[1] == -2).float().mean())))
+        log("shadow (%s, %s): %.3f ms, mismatch %.4f" % (ts, te, ms, res[-1]["occlusion_mismatch"]))
+    ms_closest = time_launches(lambda: hyb.trace_bvh(bvh, R, big, tmax_ray=TS, out=out), stream, args.reps, 2)
+    return {"config": "shadow",
+            "workload": "GI-shaped scene (%d triangles), 128^3 exact grid, %d shadow rays from the G-buffer points "
+                        "to uniform samples of a 0.3 x 0.3 area light, any hit" % (scene.n_tris, n),
+            "metric": "Mrays/s of the shadow query; occlusion mismatch against the exact any-hit triangle query",
+            "triangles_anyhit": {"ms": ms_ref, "mrays_s": n / ms_ref / 1e3},
+            "triangles_closest_hit": {"ms": ms_closest, "mrays_s": n / ms_closest / 1e3},
+            "sweep": res, "occluded_fraction": float(ref.mean())}
 
 
 if __name__ == "__main__":
