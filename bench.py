@@ -209,7 +209,7 @@ def main():
     # work counters at the chosen threshold -> algorithmic bytes per ray
     (_, _, _, _), cnt = hyb.trace_counters(bvh, sdf128, R, TMAX, tau, hyb.MODE_COMBINED)
     c = cnt.double().mean(dim=0).cpu().numpy()
-    bytes_per_ray = 24 + 16 + 64 * c[0] + 48 * c[1] + 32 * c[2]
+    bytes_per_ray = 24 + 16 + 128 * c[0] + 48 * c[1] + 32 * c[2]
 
     # timed region: K steps of the combined query at the chosen threshold
     for _ in range(args.warmup):
@@ -540,7 +540,7 @@ def bench_batch(args, torch, hyb, W, dev, stream):
     for k, it in enumerate(items):
         _, cnt = hyb.trace_counters(it["bvh"], it["sdf"], it["rays"], TMAX, taus[k], hyb.MODE_COMBINED)
         c = cnt.double().sum(dim=0).cpu().numpy()
-        total_bytes += 40.0 * meta[k]["rays"] + 64 * c[0] + 48 * c[1] + 32 * c[2]
+        total_bytes += 40.0 * meta[k]["rays"] + 128 * c[0] + 48 * c[1] + 32 * c[2]
     achieved = total_bytes / (ms_graph * 1e-3) / 1e9
     hist = {}
     for t in taus:

@@ -117,12 +117,16 @@ typedef struct {
  *   verts  host, n_verts x 3 floats (x,y,z)
  *   tris   host, n_tris x 3 int32 vertex indices; 0 <= index < n_verts
  * n_tris == 0 is allowed (every ray misses).  Degenerate triangles are kept and
- * are never hit.  Errors: NULL pointers with nonzero counts, negative counts,
- * out-of-range indices or non-finite vertices -> HYB_ERR_INVALID_ARG. */
+ * are never hit.  The tree is a binned-SAH binary BVH (used by hyb_build_sdf)
+ * collapsed to four children per node for the trace kernels.  Errors: NULL
+ * pointers with nonzero counts, negative counts, out-of-range indices or
+ * non-finite vertices -> HYB_ERR_INVALID_ARG; a tree deeper than 64 levels or
+ * whose traversal could need more than 96 stack entries ->
+ * HYB_ERR_UNSUPPORTED. */
 hyb_status hyb_build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                          void* stream, hyb_bvh* out);
 
-/* Number of BVH nodes, triangles and the tree depth. */
+/* Number of four-wide BVH nodes, triangles and the four-wide tree's depth. */
 hyb_status hyb_bvh_info(hyb_bvh bvh, int64_t* n_nodes, int64_t* n_tris, int32_t* depth);
 
 /* Build an n^3 node-centred signed distance grid from the BVH's mesh: each

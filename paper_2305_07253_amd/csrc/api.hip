@@ -11,6 +11,8 @@
 #include "api_internal.hpp"
 #include "bvh_build.hpp"
 
+static_assert(hyb::kStackDepth >= hyb::kStackDepth4, "trace stack smaller than the builder's bound");
+
 using namespace hyb_api;
 
 extern "C" {
@@ -38,18 +40,22 @@ hyb_status hyb_build_bvh(const float* verts, int64_t n_verts, const int32_t* tri
     if (!b) return HYB_ERR_OOM;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipGetDevice(&b->device);
-    b->n_nodes = static_cast<int64_t>(host.nodes.size() / 16);
+    b->n_nodes = static_cast<int64_t>(host.nodes4.size() / 32);
     b->n_tris = n_tris;
-    b->depth = host.depth;
+    b->depth = host.depth4;
     for (int a = 0; a < 3; ++a) {
         b->lo[a] = host.lo[a];
         b->hi[a] = host.hi[a];
     }
     const size_t node_bytes = host.nodes.size() * sizeof(float);
     const size_t tri_bytes = std::max<size_t>(host.tris.size(), 12) * sizeof(float);
+    const size_t node4_bytes = host.nodes4.size() * sizeof(float);
     if (e == hipSuccess) e = hipMalloc(&b->nodes, node_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b->nodes4, node4_bytes);
     if (e == hipSuccess) e = hipMalloc(&b->tris, tri_bytes);
     if (e == hipSuccess) e = hipMemcpyAsync(b->nodes, host.nodes.data(), node_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->nodes4, host.nodes4.data(), node4_bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !host.tris.empty())
         e = hipMemcpyAsync(b->tris, host.tris.data(), host.tris.size() * sizeof(float), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -72,6 +78,7 @@ hyb_status hyb_bvh_info(hyb_bvh bvh, int64_t* n_nodes, int64_t* n_tris, int32_t*
 hyb_status hyb_bvh_destroy(hyb_bvh bvh) {
     if (!bvh) return HYB_ERR_INVALID_ARG;
     if (bvh->nodes) (void)hipFree(bvh->nodes);
+    if (bvh->nodes4) (void)hipFree(bvh->nodes4);
     if (bvh->tris) (void)hipFree(bvh->tris);
     delete bvh;
     return HYB_OK;

@@ -15,9 +15,10 @@
 
 struct hyb_bvh_s {
     int device = 0;
-    float4* nodes = nullptr;
+    float4* nodes = nullptr;   // binary tree (64-byte nodes): the distance-field build's queries
+    float4* nodes4 = nullptr;  // the same tree with four children per node (128 bytes): the trace kernels
     float4* tris = nullptr;
-    int64_t n_nodes = 0, n_tris = 0;
+    int64_t n_nodes = 0, n_tris = 0;  // n_nodes counts the four-wide nodes
     int32_t depth = 0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
 };
@@ -116,7 +117,7 @@ inline void fill_trace_args(hyb::TraceArgs& a, const hyb_rays* rays, hyb_hits* h
 
 inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s) {
     if (b) {
-        a.nodes = b->nodes;
+        a.nodes = b->nodes4;
         a.tris = b->tris;
     }
     if (s) {

@@ -218,6 +218,15 @@ int build_bvh_host(const float* verts, int64_t n_verts, const int32_t* tris, int
         }
         return ~((first << 3) | n.count);
     };
+    std::vector<int32_t> leaf_refs(b.nodes.size(), 0);
+    std::vector<char> leaf_done(b.nodes.size(), 0);
+    auto leaf_of = [&](int tn) -> int32_t {  // each leaf's triangles are written once
+        if (!leaf_done[tn]) {
+            leaf_refs[tn] = leaf_ref(b.nodes[tn]);
+            leaf_done[tn] = 1;
+        }
+        return leaf_refs[tn];
+    };
     const float far = 1e30f;
     Box empty_box;
     for (int a = 0; a < 3; ++a) empty_box.lo[a] = empty_box.hi[a] = far;
@@ -236,17 +245,93 @@ int build_bvh_host(const float* verts, int64_t n_verts, const int32_t* tris, int
         n[12] = bits_as_float(lref); n[13] = bits_as_float(rref); n[14] = 0.0f; n[15] = 0.0f;
     };
 
+    // BVH4 for the trace kernels: each node takes the children of its BVH2
+    // node and replaces the inner child of largest surface area by that
+    // child's two children until it has four (or only leaves are left).
+    auto emit4 = [&]() {
+        out->nodes4.clear();
+        auto alloc4 = [&]() {
+            out->nodes4.resize(out->nodes4.size() + 32, 0.0f);
+            return static_cast<int32_t>(out->nodes4.size() / 32 - 1);
+        };
+        auto write4 = [&](int32_t slot, const int* kids, int nk) {
+            float* q = out->nodes4.data() + 32 * static_cast<size_t>(slot);
+            for (int c = 0; c < 4; ++c) {
+                const Box& bx = c < nk ? b.nodes[kids[c]].box : empty_box;
+                q[0 + c] = bx.lo[0]; q[4 + c] = bx.hi[0];
+                q[8 + c] = bx.lo[1]; q[12 + c] = bx.hi[1];
+                q[16 + c] = bx.lo[2]; q[20 + c] = bx.hi[2];
+            }
+        };
+        out->depth4 = 1;
+        out->stack4 = 0;
+        if (root < 0 || b.nodes[root].count > 0) {
+            int32_t s = alloc4();
+            int kid = root;
+            write4(s, &kid, root < 0 ? 0 : 1);
+            float* q = out->nodes4.data() + 32 * static_cast<size_t>(s);
+            for (int c = 0; c < 4; ++c) q[24 + c] = bits_as_float(c == 0 && root >= 0 ? leaf_of(root) : kEmptyRef);
+            return;
+        }
+        // `pushed`: stack entries a traversal can hold on arrival at the node
+        // (the nearer-first order pushes the other hit children of every
+        // ancestor), so its maximum bounds the traversal stack.
+        struct Item { int tn; int32_t slot; int depth; int pushed; };
+        std::vector<Item> st;
+        st.push_back({root, alloc4(), 1, 0});
+        while (!st.empty()) {
+            const Item it = st.back();
+            st.pop_back();
+            out->depth4 = std::max(out->depth4, it.depth);
+            int kids[4] = {b.nodes[it.tn].child[0], b.nodes[it.tn].child[1], -1, -1};
+            int nk = 2;
+            while (nk < 4) {
+                int best = -1;
+                float best_area = -1.0f;
+                for (int c = 0; c < nk; ++c) {
+                    const TmpNode& ch = b.nodes[kids[c]];
+                    if (ch.count == 0 && ch.box.area() > best_area) {
+                        best_area = ch.box.area();
+                        best = c;
+                    }
+                }
+                if (best < 0) break;
+                const TmpNode& ch = b.nodes[kids[best]];
+                kids[best] = ch.child[0];
+                kids[nk++] = ch.child[1];
+            }
+            write4(it.slot, kids, nk);
+            out->stack4 = std::max(out->stack4, it.pushed + nk - 1);
+            int32_t refs[4] = {kEmptyRef, kEmptyRef, kEmptyRef, kEmptyRef};
+            Item pending[4];
+            int np = 0;
+            for (int c = 0; c < nk; ++c) {
+                if (b.nodes[kids[c]].count > 0) {
+                    refs[c] = leaf_of(kids[c]);
+                } else {
+                    refs[c] = alloc4();
+                    pending[np++] = {kids[c], refs[c], it.depth + 1, it.pushed + nk - 1};
+                }
+            }
+            float* q = out->nodes4.data() + 32 * static_cast<size_t>(it.slot);
+            for (int c = 0; c < 4; ++c) q[24 + c] = bits_as_float(refs[c]);
+            for (int c = np - 1; c >= 0; --c) st.push_back(pending[c]);
+        }
+    };
+
     if (root < 0) {
         int32_t s = alloc();
         write_children(s, empty_box, kEmptyRef, empty_box, kEmptyRef);
         out->depth = 1;
+        emit4();
         return 0;
     }
     if (b.nodes[root].count > 0) {
         int32_t s = alloc();
-        int32_t lr = leaf_ref(b.nodes[root]);
+        int32_t lr = leaf_of(root);
         write_children(s, b.nodes[root].box, lr, empty_box, kEmptyRef);
         out->depth = 1;
+        emit4();
         return 0;
     }
     // iterative pre-order so the left child usually follows its parent in memory
@@ -261,7 +346,7 @@ int build_bvh_host(const float* verts, int64_t n_verts, const int32_t* tris, int
         for (int c = 0; c < 2; ++c) {
             const TmpNode& ch = b.nodes[n.child[c]];
             if (ch.count > 0) {
-                refs[c] = leaf_ref(ch);
+                refs[c] = leaf_of(n.child[c]);
             } else {
                 pending_slot[c] = alloc();
                 refs[c] = pending_slot[c];
@@ -272,7 +357,8 @@ int build_bvh_host(const float* verts, int64_t n_verts, const int32_t* tris, int
             if (pending_slot[c] >= 0) stack.push_back({n.child[c], pending_slot[c]});
     }
     out->depth = b.max_depth;
-    return 0;
+    emit4();
+    return out->stack4 > kStackDepth4 ? 4 : 0;
 }
 
 }  // namespace hyb

@@ -3,7 +3,7 @@
 // Everything here runs one ray per lane of a 64-wide CDNA wavefront:
 //   - robust ray/box slab test (Ize, "Robust BVH ray traversal", JCGT 2013)
 //   - watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013)
-//   - closest-hit BVH2 traversal with a per-lane stack in LDS (+ rare spill)
+//   - closest-hit four-wide BVH traversal with a per-lane stack in LDS (+ rare spill)
 //   - distance-field marching: conservative sphere-tracing steps g/L far from
 //     the surface, exact first root of the per-cell trilinear cubic near it.
 #pragma once
@@ -21,7 +21,7 @@ namespace hyb {
 
 constexpr int kBlock = 256;      // threads per block: 4 wavefronts
 constexpr int kLdsDepth = 16;    // stack entries per lane held in LDS
-constexpr int kStackDepth = 64;  // total stack entries per lane (LDS + spill)
+constexpr int kStackDepth = 96;  // total stack entries per lane (LDS + spill); the BVH builder bounds the need
 constexpr float kGamma3 = 3.0f * 5.9604645e-8f / (1.0f - 3.0f * 5.9604645e-8f);
 constexpr float kBoxPad = 1.0f + 2.0f * kGamma3;
 
@@ -131,15 +131,29 @@ struct Hit {
     float u, v;
 };
 
-// Closest triangle hit on [seg_lo, seg_hi] (both inclusive).  Equal t goes to
-// the smallest original triangle id, independent of traversal order.  With
-// ANY the traversal stops at the first intersection it finds (any-hit).
-// `stack` points at this lane's first LDS slot; consecutive entries are
-// `stride` ints apart (one slot per thread of the block, no bank conflicts).
+// Orders two (key, ref) pairs by key.
+HYB_HD void order2(float& ka, int& ra, float& kb, int& rb) {
+    const bool sw = kb < ka;
+    const float k = sw ? kb : ka;
+    const int r = sw ? rb : ra;
+    kb = sw ? ka : kb;
+    rb = sw ? ra : rb;
+    ka = k;
+    ra = r;
+}
+
+// Closest triangle hit on [seg_lo, seg_hi] (both inclusive) through the
+// four-wide BVH (nodes4 layout, 128-byte nodes).  Equal t goes to the smallest
+// original triangle id, independent of traversal order.  With ANY the
+// traversal stops at the first intersection it finds (any-hit).  The children
+// a node's ray hits are visited nearest first: the nearest is entered, the
+// others are pushed farthest first.  `stack` points at this lane's first LDS
+// slot; consecutive entries are `stride` ints apart (one slot per thread of
+// the block, no bank conflicts); entries beyond LDS go to a private spill area.
 template <bool COUNT, bool ANY = false, int LDS = kLdsDepth>
 HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris,
-                                           float ox, float oy, float oz, float dx, float dy, float dz,
-                                           float seg_lo, float seg_hi, int* stack, int stride, Counters& cnt) {
+                       float ox, float oy, float oz, float dx, float dy, float dz,
+                       float seg_lo, float seg_hi, int* stack, int stride, Counters& cnt) {
     Hit best;
     best.t = seg_hi;
     best.prim = -1;
@@ -153,26 +167,39 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
     int ref = 0;  // root
     for (;;) {
         if (ref >= 0) {
-            const float4* n = nodes + 4 * (int64_t)ref;
-            const float4 a = n[0], b = n[1], c = n[2], e = n[3];
+            const float4* n = nodes + 8 * (int64_t)ref;
+            const float4 lx = n[0], hx = n[1], ly = n[2], hy = n[3], lz = n[4], hz = n[5], rf = n[6];
             if (COUNT) cnt.nodes++;
-            float tn0, tf0, tn1, tf1;
             const float hi = best.t * kBoxPad;
-            box_clip(br, a.x, a.y, a.z, a.w, c.x, c.y, seg_lo, hi, tn0, tf0);
-            box_clip(br, b.x, b.y, b.z, b.w, c.z, c.w, seg_lo, hi, tn1, tf1);
-            const bool h0 = tn0 <= tf0, h1 = tn1 <= tf1;
-            const int r0 = bits_i(e.x), r1 = bits_i(e.y);
-            if (h0 && h1) {
-                const bool first0 = tn0 <= tn1;
-                const int far = first0 ? r1 : r0;
-                if (sp < LDS) stack[sp * stride] = far;
-                else spill[sp - LDS] = far;
-                ++sp;
-                ref = first0 ? r0 : r1;
+            constexpr float kNone = __builtin_inff();
+            float tn, tf;
+            box_clip(br, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, seg_lo, hi, tn, tf);
+            float k0 = tn <= tf ? tn : kNone;
+            box_clip(br, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, seg_lo, hi, tn, tf);
+            float k1 = tn <= tf ? tn : kNone;
+            box_clip(br, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, seg_lo, hi, tn, tf);
+            float k2 = tn <= tf ? tn : kNone;
+            box_clip(br, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, seg_lo, hi, tn, tf);
+            float k3 = tn <= tf ? tn : kNone;
+            int r0 = bits_i(rf.x), r1 = bits_i(rf.y), r2 = bits_i(rf.z), r3 = bits_i(rf.w);
+            // sorting network, nearest first; misses (+inf) sink to the end
+            order2(k0, r0, k1, r1);
+            order2(k2, r2, k3, r3);
+            order2(k0, r0, k2, r2);
+            order2(k1, r1, k3, r3);
+            order2(k1, r1, k2, r2);
+            if (k0 < kNone) {
+                const int push[3] = {r3, r2, r1};
+                const bool take[3] = {k3 < kNone, k2 < kNone, k1 < kNone};
+                for (int c = 0; c < 3; ++c) {
+                    if (!take[c]) continue;
+                    if (sp < LDS) stack[sp * stride] = push[c];
+                    else spill[sp - LDS] = push[c];
+                    ++sp;
+                }
+                ref = r0;
                 continue;
             }
-            if (h0) { ref = r0; continue; }
-            if (h1) { ref = r1; continue; }
         } else {
             const int info = ~ref;
             const int first = info >> 3, count = info & 7;

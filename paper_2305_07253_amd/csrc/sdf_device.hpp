@@ -88,14 +88,17 @@ HYB_HD int crossing(D3 o, D3 D, D3 a, D3 b, D3 c) {
     return ddot(D, n) > 0.0 ? 1 : -1;
 }
 
+// BVH2 queries push at most one entry per level, and the BVH2 is at most 64 deep.
+constexpr int kStack2 = 64;
+
 HYB_HD double sdf_node_value(const float4* __restrict__ nodes, const float4* __restrict__ tris, D3 p,
                              int exterior_solid) {
-    int stack[kStackDepth];
+    int stack[kStack2];
 
     // nearest triangle: children in order of box distance; a popped subtree is
     // skipped when its box is no closer than the best triangle found since
     double best = __builtin_inf();
-    double dstack[kStackDepth];
+    double dstack[kStack2];
     int sp = 0;
     int ref = 0;
     for (;;) {

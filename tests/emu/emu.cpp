@@ -64,9 +64,11 @@ int main(int argc, char** argv) {
         return 3;
     }
     // exact-size device-layout buffers so the sanitizer sees any overrun
-    std::vector<float4> nodes(bvh.nodes.size() / 4), tri4(bvh.tris.size() / 4);
+    std::vector<float4> nodes(bvh.nodes.size() / 4), nodes4(bvh.nodes4.size() / 4), tri4(bvh.tris.size() / 4);
     for (size_t i = 0; i < nodes.size(); ++i)
         nodes[i] = make_float4(bvh.nodes[4 * i], bvh.nodes[4 * i + 1], bvh.nodes[4 * i + 2], bvh.nodes[4 * i + 3]);
+    for (size_t i = 0; i < nodes4.size(); ++i)
+        nodes4[i] = make_float4(bvh.nodes4[4 * i], bvh.nodes4[4 * i + 1], bvh.nodes4[4 * i + 2], bvh.nodes4[4 * i + 3]);
     for (size_t i = 0; i < tri4.size(); ++i)
         tri4[i] = make_float4(bvh.tris[4 * i], bvh.tris[4 * i + 1], bvh.tris[4 * i + 2], bvh.tris[4 * i + 3]);
 
@@ -121,7 +123,7 @@ int main(int argc, char** argv) {
     a.tmax_ray = (has_tmin & 2) ? tmaxr.data() : nullptr;
     a.tau_end = par[7];
     a.t = t.data(); a.prim = prim.data(); a.u = u.data(); a.v = v.data(); a.counts = counts.data();
-    a.nodes = nodes.data();
+    a.nodes = nodes4.data();
     a.tris = tri4.data();
     a.sdf = grid.empty() ? nullptr
             : (fmt == 1 ? static_cast<const void*>(b16.data())
