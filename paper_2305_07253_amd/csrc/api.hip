@@ -50,6 +50,14 @@ hyb_status hyb_build_bvh(const float* verts, int64_t n_verts, const int32_t* tri
     const size_t node_bytes = host.nodes.size() * sizeof(float);
     const size_t tri_bytes = std::max<size_t>(host.tris.size(), 12) * sizeof(float);
     const size_t node4_bytes = host.nodes4.size() * sizeof(float);
+    const size_t entry_bytes = host.entry.size() * sizeof(int32_t);
+    b->entry_res = host.entry_res;
+    b->entry_levels = host.entry_levels;
+    b->entry_size = host.entry_size;
+    for (int a = 0; a < 3; ++a) b->entry_lo[a] = host.entry_lo[a];
+    if (e == hipSuccess && entry_bytes) e = hipMalloc(&b->entry, entry_bytes);
+    if (e == hipSuccess && entry_bytes)
+        e = hipMemcpyAsync(b->entry, host.entry.data(), entry_bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMalloc(&b->nodes, node_bytes);
     if (e == hipSuccess) e = hipMalloc(&b->nodes4, node4_bytes);
     if (e == hipSuccess) e = hipMalloc(&b->tris, tri_bytes);
@@ -79,6 +87,7 @@ hyb_status hyb_bvh_destroy(hyb_bvh bvh) {
     if (!bvh) return HYB_ERR_INVALID_ARG;
     if (bvh->nodes) (void)hipFree(bvh->nodes);
     if (bvh->nodes4) (void)hipFree(bvh->nodes4);
+    if (bvh->entry) (void)hipFree(bvh->entry);
     if (bvh->tris) (void)hipFree(bvh->tris);
     delete bvh;
     return HYB_OK;

@@ -17,6 +17,9 @@ struct hyb_bvh_s {
     int device = 0;
     float4* nodes = nullptr;   // binary tree (64-byte nodes): the distance-field build's queries
     float4* nodes4 = nullptr;  // the same tree with four children per node (128 bytes): the trace kernels
+    int32_t* entry = nullptr;  // traversal entry pyramid (BvhHost::entry)
+    float entry_lo[3] = {0, 0, 0}, entry_size = 0.0f;
+    int32_t entry_res = 0, entry_levels = 0;
     float4* tris = nullptr;
     int64_t n_nodes = 0, n_tris = 0;  // n_nodes counts the four-wide nodes
     int32_t depth = 0;
@@ -118,6 +121,13 @@ inline void fill_trace_args(hyb::TraceArgs& a, const hyb_rays* rays, hyb_hits* h
 inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s) {
     if (b) {
         a.nodes = b->nodes4;
+        a.entry = b->entry_res ? b->entry : nullptr;
+        a.entry_lo_x = b->entry_lo[0];
+        a.entry_lo_y = b->entry_lo[1];
+        a.entry_lo_z = b->entry_lo[2];
+        a.entry_inv = b->entry_res ? 1.0f / b->entry_size : 0.0f;
+        a.entry_res = b->entry_res;
+        a.entry_levels = b->entry_levels;
         a.tris = b->tris;
     }
     if (s) {

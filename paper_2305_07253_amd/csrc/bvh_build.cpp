@@ -162,6 +162,104 @@ inline float bits_as_float(int32_t v) {
     return f;
 }
 
+constexpr int kEntryRes = 64;
+
+// Entry points of BvhHost (see the header): the finest level by a box query
+// per voxel, the coarser ones as the common ancestor of their 8 children.
+void build_entries(BvhHost* out) {
+    out->entry.clear();
+    out->entry_res = 0;
+    out->entry_levels = 0;
+    const size_t n4 = out->nodes4.size() / 32;
+    float ext = 0.0f;
+    for (int a = 0; a < 3; ++a) ext = std::max(ext, out->hi[a] - out->lo[a]);
+    if (n4 == 0 || !(ext > 0.0f)) return;
+    const float* nd = out->nodes4.data();
+    auto ref_of = [&](size_t node, int c) {
+        int32_t r;
+        std::memcpy(&r, nd + 32 * node + 24 + c, 4);
+        return r;
+    };
+    // parents and depths of nodes and leaves
+    // a leaf is identified by its first triangle, (~ref) >> 3
+    std::vector<int32_t> parent(n4, -1), depth(n4, 0), leaf_parent(out->tris.size() / 12 + 1, -1);
+    for (size_t i = 0; i < n4; ++i)  // children come after their parent in the array
+        for (int c = 0; c < 4; ++c) {
+            const int32_t r = ref_of(i, c);
+            if (r == kEmptyRef) continue;
+            if (r >= 0) {
+                parent[r] = static_cast<int32_t>(i);
+                depth[r] = depth[i] + 1;
+            } else {
+                leaf_parent[(~r) >> 3] = static_cast<int32_t>(i);
+            }
+        }
+    auto depth_of = [&](int32_t r) { return r >= 0 ? depth[r] : depth[leaf_parent[(~r) >> 3]] + 1; };
+    auto up = [&](int32_t r) { return r >= 0 ? parent[r] : leaf_parent[(~r) >> 3]; };
+    auto lca = [&](int32_t a, int32_t b) {
+        if (a == kEmptyRef) return b;
+        if (b == kEmptyRef) return a;
+        int da = depth_of(a), db = depth_of(b);
+        while (da > db) { a = up(a); --da; }
+        while (db > da) { b = up(b); --db; }
+        while (a != b) { a = up(a); b = up(b); }
+        return a;
+    };
+
+    const int E = kEntryRes;
+    const float size = ext / static_cast<float>(E) * (1.0f + 1e-4f);
+    for (int a = 0; a < 3; ++a) out->entry_lo[a] = out->lo[a] - 0.5f * (size * E - (out->hi[a] - out->lo[a]));
+    out->entry_size = size;
+    int levels = 0;
+    size_t total = 0;
+    for (int e = E; e >= 1; e >>= 1) {
+        total += static_cast<size_t>(e) * e * e;
+        ++levels;
+    }
+    out->entry.assign(total, kEmptyRef);
+    // every leaf joins the entry of each finest voxel its box overlaps, the
+    // box grown by a margin (FP32 rounding of segment end points is far below it)
+    const double margin = 1e-3 * size;
+    for (size_t i = 0; i < n4; ++i)
+        for (int c = 0; c < 4; ++c) {
+            const int32_t r = ref_of(i, c);
+            if (r == kEmptyRef || r >= 0) continue;
+            const float* q = nd + 32 * i;
+            int v0[3], v1[3];
+            for (int a = 0; a < 3; ++a) {
+                const double qlo = q[8 * a + c], qhi = q[8 * a + 4 + c];
+                const double slack = margin + 1e-6 * (1.0 + std::max(std::fabs(qlo), std::fabs(qhi)));
+                const double u0 = (qlo - slack - out->entry_lo[a]) / size, u1 = (qhi + slack - out->entry_lo[a]) / size;
+                v0[a] = static_cast<int>(std::floor(std::min(std::max(u0, 0.0), E - 1.0)));
+                v1[a] = static_cast<int>(std::floor(std::min(std::max(u1, 0.0), E - 1.0)));
+            }
+            for (int z = v0[2]; z <= v1[2]; ++z)
+                for (int y = v0[1]; y <= v1[1]; ++y)
+                    for (int x = v0[0]; x <= v1[0]; ++x) {
+                        int32_t& slot = out->entry[x + static_cast<size_t>(E) * (y + static_cast<size_t>(E) * z)];
+                        slot = lca(slot, r);
+                    }
+        }
+    size_t off = 0;
+    for (int e = E; e > 1; e >>= 1) {
+        const size_t next = off + static_cast<size_t>(e) * e * e;
+        const int h = e / 2;
+        for (int z = 0; z < h; ++z)
+            for (int y = 0; y < h; ++y)
+                for (int x = 0; x < h; ++x) {
+                    int32_t acc = kEmptyRef;
+                    for (int c = 0; c < 8; ++c) {
+                        const int cx = 2 * x + (c & 1), cy = 2 * y + ((c >> 1) & 1), cz = 2 * z + (c >> 2);
+                        acc = lca(acc, out->entry[off + cx + static_cast<size_t>(e) * (cy + static_cast<size_t>(e) * cz)]);
+                    }
+                    out->entry[next + x + static_cast<size_t>(h) * (y + static_cast<size_t>(h) * z)] = acc;
+                }
+        off = next;
+    }
+    out->entry_res = E;
+    out->entry_levels = levels;
+}
+
 }  // namespace
 
 int build_bvh_host(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris, BvhHost* out) {
@@ -324,6 +422,7 @@ int build_bvh_host(const float* verts, int64_t n_verts, const int32_t* tris, int
         write_children(s, empty_box, kEmptyRef, empty_box, kEmptyRef);
         out->depth = 1;
         emit4();
+        build_entries(out);
         return 0;
     }
     if (b.nodes[root].count > 0) {
@@ -332,6 +431,7 @@ int build_bvh_host(const float* verts, int64_t n_verts, const int32_t* tris, int
         write_children(s, b.nodes[root].box, lr, empty_box, kEmptyRef);
         out->depth = 1;
         emit4();
+        build_entries(out);
         return 0;
     }
     // iterative pre-order so the left child usually follows its parent in memory
@@ -358,7 +458,9 @@ int build_bvh_host(const float* verts, int64_t n_verts, const int32_t* tris, int
     }
     out->depth = b.max_depth;
     emit4();
-    return out->stack4 > kStackDepth4 ? 4 : 0;
+    if (out->stack4 > kStackDepth4) return 4;
+    build_entries(out);
+    return 0;
 }
 
 }  // namespace hyb

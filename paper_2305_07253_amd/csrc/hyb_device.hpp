@@ -153,7 +153,7 @@ HYB_HD void order2(float& ka, int& ra, float& kb, int& rb) {
 template <bool COUNT, bool ANY = false, int LDS = kLdsDepth>
 HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                        float ox, float oy, float oz, float dx, float dy, float dz,
-                       float seg_lo, float seg_hi, int* stack, int stride, Counters& cnt) {
+                       float seg_lo, float seg_hi, int* stack, int stride, Counters& cnt, int start = 0) {
     Hit best;
     best.t = seg_hi;
     best.prim = -1;
@@ -164,7 +164,7 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
     static_assert(LDS > 0 && LDS < kStackDepth, "LDS part of the stack out of range");
     int spill[kStackDepth - LDS];
     int sp = 0;
-    int ref = 0;  // root
+    int ref = start;  // the root, or a subtree holding every triangle the segment can reach
     for (;;) {
         if (ref >= 0) {
             const float4* n = nodes + 8 * (int64_t)ref;
@@ -663,6 +663,38 @@ inline float certified_slack(float h, int n) {
     return 2.0f * (0.8660254f * h * (1.0f + 1e-6f) + q);
 }
 
+// Where a traversal of the segment [t0, t1] may start: the entry of the
+// finest voxel of the pyramid that holds the whole segment, grown by a margin
+// over the FP32 rounding of its end points (every triangle the segment can hit
+// overlaps that voxel, so it lies under the voxel's entry), else the root.
+// Parts of the segment outside the pyramid's box reach no triangle, so the end
+// points are clamped into it.
+HYB_HD int entry_node(const TraceArgs& a, float ox, float oy, float oz, float dx, float dy, float dz, float t0,
+                      float t1) {
+    if (a.entry_res == 0 || !(t1 < __builtin_inff()) || !(t0 <= t1)) return 0;
+    const int E = a.entry_res;
+    int ia[3], ib[3];
+    const float o[3] = {ox, oy, oz}, d[3] = {dx, dy, dz}, lo[3] = {a.entry_lo_x, a.entry_lo_y, a.entry_lo_z};
+    for (int k = 0; k < 3; ++k) {
+        const float p0 = fmaf(t0, d[k], o[k]), p1 = fmaf(t1, d[k], o[k]);
+        const float m = 1e-6f * (1.0f + fmaxf(fabsf(p0), fabsf(p1)));
+        const float u0 = (fminf(p0, p1) - m - lo[k]) * a.entry_inv;
+        const float u1 = (fmaxf(p0, p1) + m - lo[k]) * a.entry_inv;
+        ia[k] = (int)floorf(fminf(fmaxf(u0, 0.0f), (float)(E - 1)));
+        ib[k] = (int)floorf(fminf(fmaxf(u1, 0.0f), (float)(E - 1)));
+    }
+    int level = 0, off = 0;
+    for (; level + 1 < a.entry_levels; ++level) {
+        if ((ia[0] >> level) == (ib[0] >> level) && (ia[1] >> level) == (ib[1] >> level) &&
+            (ia[2] >> level) == (ib[2] >> level))
+            break;
+        const int e = E >> level;
+        off += e * e * e;
+    }
+    const int e = E >> level;
+    return a.entry[off + (ia[0] >> level) + e * ((ia[1] >> level) + e * (ia[2] >> level))];
+}
+
 // One ray of a query (the body of the trace kernels).
 template <int MODE, int FMT, bool COUNT, int LDS = kLdsDepth>
 HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
@@ -680,7 +712,8 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
         const Grid g = {a.sdf, a.scales, a.n_grid, a.nb, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e,
                         1.0 / (double)a.h};
         if (MODE == kBvhOnly) {
-            hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, tmax, stack, stride, cnt);
+            hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, tmax, stack, stride, cnt,
+                                                 entry_node(a, ox, oy, oz, dx, dy, dz, tmin, tmax));
         } else if (MODE == kDfOnly) {
             const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, tmin, tmax, cnt);
             if (t < __builtin_inff()) {
@@ -701,15 +734,19 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
                 }
             }
             if (hit.prim == -1 && t1 > tmin)
-                hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt);
+                hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt,
+                                                    entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1));
             if (hit.prim == -1 && tmax > t2)
-                hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, t2, tmax, stack, stride, cnt);
+                hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, t2, tmax, stack, stride, cnt,
+                                                    entry_node(a, ox, oy, oz, dx, dy, dz, t2, tmax));
         } else {
             // Eq. (2) with two sub-queries processed in order (first hit):
             // triangles on [tmin, t1]; the distance field on [t1, tmax] only
             // when the first sub-query found nothing.
             const float t1 = fminf(fmaf(a.tau, a.h, tmin), tmax);
-            if (t1 > tmin) hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt);
+            if (t1 > tmin)
+                hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride,
+                                                     cnt, entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1));
             if (hit.prim < 0 && (t1 < tmax || a.tau == 0.0f)) {
                 const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, tmax, cnt);
                 if (t < __builtin_inff()) {

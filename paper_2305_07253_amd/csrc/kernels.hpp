@@ -17,8 +17,11 @@ struct TraceArgs {
     float *u, *v;
     int32_t* counts;  // 3 per ray or null
     // scene
-    const float4* nodes;
+    const float4* nodes;  // four-wide BVH
     const float4* tris;
+    const int32_t* entry;  // traversal entry pyramid (null: start at the root)
+    float entry_lo_x, entry_lo_y, entry_lo_z, entry_inv;  // origin, 1 / finest voxel side
+    int32_t entry_res, entry_levels;
     const void* sdf;      // samples in the grid's storage format
     const float* scales;  // I8 block scales or null
     int32_t fmt;          // SdfFormat

@@ -124,6 +124,13 @@ int main(int argc, char** argv) {
     a.tau_end = par[7];
     a.t = t.data(); a.prim = prim.data(); a.u = u.data(); a.v = v.data(); a.counts = counts.data();
     a.nodes = nodes4.data();
+    a.entry = bvh.entry_res ? bvh.entry.data() : nullptr;
+    a.entry_lo_x = bvh.entry_lo[0];
+    a.entry_lo_y = bvh.entry_lo[1];
+    a.entry_lo_z = bvh.entry_lo[2];
+    a.entry_inv = bvh.entry_res ? 1.0f / bvh.entry_size : 0.0f;
+    a.entry_res = bvh.entry_res;
+    a.entry_levels = bvh.entry_levels;
     a.tris = tri4.data();
     a.sdf = grid.empty() ? nullptr
             : (fmt == 1 ? static_cast<const void*>(b16.data())
