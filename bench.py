@@ -306,36 +306,6 @@ def run_extra(args):
     print(json.dumps(line), flush=True)
 
 
-def oracle_grid_sparse(oracle, scene, g4, n, rays, tmax):
-    """The oracle's own exact samples at every node of the cells the rays'
-    segments [0, tmax] can cross (found by sampling each segment every h/16 and
-    taking the neighbouring cells too); NaN elsewhere, so a read outside shows."""
-    h = np.float64(g4[3])
-    lo = g4[:3].astype(np.float64)
-    ts = np.arange(0.0, tmax + h / 16, h / 16)
-    cells = []
-    o, d = rays.o.astype(np.float64), rays.d.astype(np.float64)
-    for c0 in range(0, rays.n, 256):
-        log("oracle cells: rays %d / %d" % (c0, rays.n))
-        p = o[c0:c0 + 256, None, :] + ts[None, :, None] * d[c0:c0 + 256, None, :]
-        c = np.floor((p - lo) / h).astype(np.int64).reshape(-1, 3)
-        for dz in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dx in (-1, 0, 1):
-                    cc = np.clip(c + np.array([dx, dy, dz]), 0, n - 2)
-                    cells.append(np.unique(cc[:, 0] + n * (cc[:, 1] + n * cc[:, 2])))
-    cells = np.unique(np.concatenate(cells))
-    ci, cj, ck = cells % n, (cells // n) % n, cells // (n * n)
-    nodes = np.unique(np.concatenate([(ci + dx) + n * ((cj + dy) + n * (ck + dz))
-                                      for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]))
-    grid = np.full(n ** 3, np.nan, dtype=np.float32)
-    step = 1 << 18
-    for c0 in range(0, len(nodes), step):
-        log("oracle samples: %d / %d nodes" % (c0, len(nodes)))
-        grid[nodes[c0:c0 + step]] = oracle.sdf_nodes(scene, g4, n, nodes=nodes[c0:c0 + step]).astype(np.float32)
-    return grid.reshape(n, n, n), len(nodes)
-
-
 def bench_precision(args, torch, hyb, W, dev, stream):
     """2M-triangle scene, 256^3 grid stored FP32 / FP16 / int8 + block scales,
     4 rays per pixel at 1080p; rays/s per format and each format's t error
@@ -365,7 +335,7 @@ def bench_precision(args, torch, hyb, W, dev, stream):
     idx = np.linspace(0, rays.n - 1, args.oracle_sample).astype(np.int64)
     sub = rays.subset(idx)
     t0 = time.time()
-    og, n_nodes = oracle_grid_sparse(oracle, scene, g4, 256, sub, TMAX)
+    og, n_nodes = oracle.sdf_grid_sparse(scene, g4, 256, sub.o, sub.d, TMAX, progress=log)
     log("oracle: exact samples at %d nodes (%.1fs)" % (n_nodes, time.time() - t0))
     res = {}
     for tau in (0.0, 1.0):
@@ -388,7 +358,8 @@ def bench_precision(args, torch, hyb, W, dev, stream):
                 name, tau, ms, rays.n / ms / 1e3, same.mean(), rel.mean(), np.percentile(rel, 99)))
     return {"config": "precision", "workload": "%d-triangle room, 256^3 grid (h=1/251), %d rays (4 per pixel, "
             "1920x1080 G-buffer), tmax 0.5" % (scene.n_tris, rays.n), "oracle_sample": int(len(idx)),
-            "grid_bytes": {"f32": 4 * 256 ** 3, "f16": 2 * 256 ** 3, "i8": 256 ** 3 + 4 * 32 ** 3},
+            "kernel_store_bytes": {"f32": 4 * 27 * 128 ** 3, "f16": 2 * 8 * 255 ** 3, "i8": 8 * 255 ** 3 + 4 * 32 ** 3},
+            "linear_fp32_bytes": 4 * 256 ** 3,
             "results": res}
 
 

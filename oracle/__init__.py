@@ -256,3 +256,37 @@ def df_grad(grid, grid4, rays_soa, t_hit, a=0.0, b=np.inf):
     dt = np.empty((n, 8))
     lib().oracle_df_grad(_p(g), g.shape[-1], _p(_f32(grid4)), _p(r), n, _p(a), _p(b), _p(th), _p(nodes), _p(dt))
     return nodes, dt
+
+
+def sdf_grid_sparse(scene, grid4, n, rays_o, rays_d, tmax, progress=None):
+    """Exact samples (sdf_nodes) at every node of the cells that segments
+    [0, tmax] of the given rays can cross, NaN elsewhere, so that a query
+    reading any other node shows it.  The cells are found by sampling each
+    segment every h/16 and adding all 26 neighbours of every cell met.
+    Returns (grid (n,n,n) float32, number of nodes computed)."""
+    h = np.float64(grid4[3])
+    lo = np.asarray(grid4[:3], np.float64)
+    ts = np.arange(0.0, tmax + h / 16, h / 16)
+    o, d = np.asarray(rays_o, np.float64), np.asarray(rays_d, np.float64)
+    cells = []
+    for c0 in range(0, len(o), 256):
+        if progress:
+            progress("oracle cells: rays %d / %d" % (c0, len(o)))
+        p = o[c0:c0 + 256, None, :] + ts[None, :, None] * d[c0:c0 + 256, None, :]
+        c = np.floor((p - lo) / h).astype(np.int64).reshape(-1, 3)
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    cc = np.clip(c + np.array([dx, dy, dz]), 0, n - 2)
+                    cells.append(np.unique(cc[:, 0] + n * (cc[:, 1] + n * cc[:, 2])))
+    cells = np.unique(np.concatenate(cells))
+    ci, cj, ck = cells % n, (cells // n) % n, cells // (n * n)
+    nodes = np.unique(np.concatenate([(ci + dx) + n * ((cj + dy) + n * (ck + dz))
+                                      for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)]))
+    grid = np.full(n ** 3, np.nan, dtype=np.float32)
+    step = 1 << 18
+    for c0 in range(0, len(nodes), step):
+        if progress:
+            progress("oracle samples: %d / %d nodes" % (c0, len(nodes)))
+        grid[nodes[c0:c0 + step]] = sdf_nodes(scene, grid4, n, nodes=nodes[c0:c0 + step]).astype(np.float32)
+    return grid.reshape(n, n, n), len(nodes)

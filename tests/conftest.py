@@ -33,3 +33,14 @@ def tiny(orc):
     free = W.uniform_rays(scene, 4096, 11)
     surf = W.offset_rays(W.surface_points(scene, 4096, 12), 1e-5, 13)
     return dict(scene=scene, grid4=g4, grid=grid, N=32, free=free, surf=surf, tmax=2.0)
+
+
+@pytest.fixture(scope="session")
+def gi_exact(orc):
+    """GI-shaped scene (188,572 triangles) with the oracle's exact 128^3 grid
+    (computed once per session; the GPU tests of several modules use it)."""
+    from paper_2305_07253_amd import workloads as W
+    scene = W.gi_scene(2)
+    g4 = W.room_grid(128)
+    print("building the oracle's exact 128^3 grid", flush=True)
+    return dict(scene=scene, g4=g4, grid=orc.sdf_grid(scene, g4, 128))

@@ -162,17 +162,16 @@ def test_empty_and_degenerate_meshes(hyb, orc):
 # ---------------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
-def gi(hyb, orc):
+def gi(hyb, orc, gi_exact):
     from paper_2305_07253_amd import workloads as W
-    sc = W.gi_scene(2)
-    g4 = W.room_grid(128)
+    sc = gi_exact["scene"]
+    g4 = gi_exact["g4"]
     gb = W.gbuffer(sc, 1920, 1080)
     rays = W.gbuffer_rays(gb, 21)
     bvh = hyb.build_bvh(sc.verts, sc.tris)
     sdf = hyb.build_sdf(bvh, 128, g4, exterior_solid=True)
     sample = np.arange(0, rays.n, 32 * 16)  # 4,050 rays, fixed stride in tile order
-    print("building the oracle's exact 128^3 grid", flush=True)
-    oracle_grid = orc.sdf_grid(sc, g4, 128)
+    oracle_grid = gi_exact["grid"]
     return dict(scene=sc, g4=g4, rays=rays, bvh=bvh, sdf=sdf, dev=to_dev(rays.soa()), sample=sample,
                 oracle_grid=oracle_grid)
 
