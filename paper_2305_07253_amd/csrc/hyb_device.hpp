@@ -270,11 +270,15 @@ struct Brick {
         return b * b * b * kNodes;
     }
 
-    // Storage slot of corner 0 (the node (i, j, k)) of cell (i, j, k).
+    // Storage slot of corner 0 (the node (i, j, k)) of cell (i, j, k); cells
+    // are never negative, and a grid has fewer than 2^30 bricks, so only the
+    // last product needs 64 bits.
     HYB_HD static int64_t cell_slot(int i, int j, int k, int nbk) {
-        const int bi = i / kCells, bj = j / kCells, bk = k / kCells;
-        const int r = (i - bi * kCells) + kSide * ((j - bj * kCells) + kSide * (k - bk * kCells));
-        return (((int64_t)bk * nbk + bj) * nbk + bi) * kNodes + r;
+        const uint32_t ui = (uint32_t)i, uj = (uint32_t)j, uk = (uint32_t)k, nb = (uint32_t)nbk;
+        const uint32_t bi = ui / kCells, bj = uj / kCells, bk = uk / kCells;
+        const uint32_t r = (ui - bi * kCells) + kSide * ((uj - bj * kCells) + kSide * (uk - bk * kCells));
+        const uint32_t brick = (bk * nb + bj) * nb + bi;
+        return (int64_t)((uint64_t)brick * (uint32_t)kNodes + r);
     }
 
     // The node stored in slot s; false for a padding slot.
