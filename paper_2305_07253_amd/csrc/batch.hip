@@ -26,7 +26,7 @@ namespace {
 constexpr int kWave = 64;
 
 template <int FMT, int LDS>
-__global__ __launch_bounds__(kBlock) void k_trace_batch(BatchArgs b) {
+__global__ __launch_bounds__(kBlock) void k_trace_batch(BatchArgs b, const TraceArgs* __restrict__ scenes) {
     extern __shared__ int s_stack[];
     const int lane = threadIdx.x & (kWave - 1);
     for (;;) {
@@ -41,17 +41,10 @@ __global__ __launch_bounds__(kBlock) void k_trace_batch(BatchArgs b) {
             if (b.item_start[mid] <= w) lo = mid;
             else hi = mid;
         }
-        // The scene's arguments are the same for the whole wavefront: keep
-        // them in scalar registers.
-        struct Words {
-            int v[sizeof(TraceArgs) / 4];
-        };
-        static_assert(sizeof(TraceArgs) % 4 == 0, "TraceArgs must be a whole number of dwords");
-        Words words = *reinterpret_cast<const Words*>(b.scenes + lo);
-#pragma unroll
-        for (int k = 0; k < (int)(sizeof(TraceArgs) / 4); ++k) words.v[k] = __builtin_amdgcn_readfirstlane(words.v[k]);
-        TraceArgs a;
-        __builtin_memcpy(&a, &words, sizeof(a));
+        // The scene's arguments are the same for the whole wavefront (lo is
+        // uniform) and the table is never written by the kernel: its fields
+        // are read with scalar loads where they are used.
+        const TraceArgs& a = scenes[__builtin_amdgcn_readfirstlane(lo)];
         const int64_t base = (int64_t)(w - b.item_start[lo]) * b.rays_per_item;
         for (int k = 0; k < b.rays_per_item; k += kWave) {
             const int64_t i = base + k + lane;
@@ -220,7 +213,8 @@ hipError_t launch_eager(hyb_batch_s* b, hipStream_t stream) {
     void* reset_args[] = {&b->d_queue};
     hipError_t e = hipLaunchKernel(hyb::queue_reset_kernel(), dim3(1), dim3(64), reset_args, 0, stream);
     if (e != hipSuccess || b->kargs.n_items == 0) return e;
-    void* trace_args[] = {&b->kargs};
+    const hyb::TraceArgs* scenes = b->d_args;
+    void* trace_args[] = {&b->kargs, &scenes};
     return hipLaunchKernel(hyb::batch_kernel(b->fmt, b->cfg.lds_depth), b->grid, dim3(hyb::kBlock), trace_args,
                            hyb::batch_lds_bytes(b->cfg.lds_depth), stream);
 }
@@ -239,8 +233,9 @@ hipError_t build_graph(hyb_batch_s* b) {
     p0.blockDim = dim3(64);
     p0.kernelParams = reset_args;
     e = hipGraphAddKernelNode(&reset_node, b->graph, nullptr, 0, &p0);
+    const hyb::TraceArgs* scenes = b->d_args;
     if (e == hipSuccess && b->kargs.n_items > 0) {
-        void* trace_args[] = {&b->kargs};
+        void* trace_args[] = {&b->kargs, &scenes};
         hipKernelNodeParams p1;
         std::memset(&p1, 0, sizeof(p1));
         p1.func = const_cast<void*>(hyb::batch_kernel(b->fmt, b->cfg.lds_depth));
