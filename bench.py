@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiling driver: a 256 MiB copy probe, then --steps launches of the combined, "
                          "triangle-only and DF-only kernels; no sweep, no JSON line")
-    ap.add_argument("--config", default="gi", choices=["gi", "diff", "precision", "batch", "shadow"],
+    ap.add_argument("--config", default="gi", choices=["gi", "diff", "precision", "batch", "shadow", "ao"],
                     help="gi: the headline combined-query benchmark (one JSON line with value); the others print "
                          "their own JSON line for the differentiation, precision, batching and shadow workloads")
     ap.add_argument("--adam-steps", type=int, default=200)
@@ -301,6 +301,8 @@ def run_extra(args):
         line = bench_batch(args, torch, hyb, W, dev, stream)
     elif args.config == "shadow":
         line = bench_shadow(args, torch, hyb, W, dev, stream)
+    elif args.config == "ao":
+        line = bench_ao(args, torch, hyb, W, dev, stream)
     else:
         raise SystemExit("config %s not implemented" % args.config)
     print(json.dumps(line), flush=True)
@@ -574,6 +576,46 @@ def bench_shadow(args, torch, hyb, W, dev, stream):
             "triangles_anyhit": {"ms": ms_ref, "mrays_s": n / ms_ref / 1e3},
             "triangles_closest_hit": {"ms": ms_closest, "mrays_s": n / ms_closest / 1e3},
             "sweep": res, "occluded_fraction": float(ref.mean())}
+
+
+
+def bench_ao(args, torch, hyb, W, dev, stream):
+    """Occlusion (AO) rays of several lengths on the GI-shaped scene: first hit
+    on [0, t_ao] from the G-buffer points, triangles only against the combined
+    query at thresholds 0.5, 1, 2 voxels and the DF-only baseline (from p + h n),
+    each with its artefact rate against the triangles-only hits."""
+    scene = W.gi_scene(2)
+    g4 = W.room_grid(128)
+    h = float(g4[3])
+    gb = W.gbuffer(scene, args.width, args.height)
+    rays = W.gbuffer_rays(gb, 51)
+    rb = W.rebias(rays, gb, h)
+    bvh = hyb.build_bvh(scene.verts, scene.tris)
+    sdf = hyb.build_sdf(bvh, 128, g4)
+    R, RB = torch.from_numpy(rays.soa()).to(dev), torch.from_numpy(rb.soa()).to(dev)
+    n = rays.n
+    out = hyb.alloc_hits(n)
+    o_np, d_np, ob_np = rays.o.astype(np.float64), rays.d.astype(np.float64), rb.o.astype(np.float64)
+    res = []
+    for t_ao in (0.05, 0.1, 0.25, 0.5, 1.0):
+        ms_bvh = time_launches(lambda: hyb.trace_bvh(bvh, R, t_ao, out=out), stream, args.reps, 2)
+        ref_t, ref_p = out[0].cpu().numpy().astype(np.float64), out[1].cpu().numpy()
+        row = dict(t_ao=t_ao, t_ao_voxels=t_ao / h, triangles_ms=ms_bvh, occluded=float((ref_p != -1).mean()))
+        for tau in (0.5, 1.0, 2.0):
+            ms = time_launches(lambda: hyb.trace(bvh, sdf, R, t_ao, tau, out=out), stream, args.reps, 2)
+            a = artefacts(out[0].cpu().numpy().astype(np.float64), out[1].cpu().numpy(), o_np, d_np, ref_t, ref_p,
+                          o_np, h)
+            row["tau%g" % tau] = dict(ms=ms, speedup=ms_bvh / ms, artefacts=a["rate"])
+        ms = time_launches(lambda: hyb.trace_df(sdf, RB, t_ao, out=out), stream, args.reps, 2)
+        a = artefacts(out[0].cpu().numpy().astype(np.float64), out[1].cpu().numpy(), ob_np, d_np, ref_t, ref_p,
+                      o_np, h)
+        row["df_only"] = dict(ms=ms, speedup=ms_bvh / ms, artefacts=a["rate"])
+        log("t_ao %.2f: triangles %.3f ms; tau 1 %.3f ms (x%.2f, artefacts %.4f); DF only %.3f ms (artefacts %.4f)" % (
+            t_ao, ms_bvh, row["tau1"]["ms"], row["tau1"]["speedup"], row["tau1"]["artefacts"], ms, a["rate"]))
+        res.append(row)
+    return {"config": "ao", "workload": "GI-shaped scene (%d triangles), 128^3 exact grid, %d cosine AO rays from the "
+            "G-buffer points, first hit on [0, t_ao]" % (scene.n_tris, n),
+            "metric": "tracing time per AO distance: triangles only vs combined vs DF only", "sweep": res}
 
 
 if __name__ == "__main__":
