@@ -675,7 +675,9 @@ inline float certified_slack(float h, int n) {
 // points are clamped into it.
 HYB_HD int entry_node(const TraceArgs& a, float ox, float oy, float oz, float dx, float dy, float dz, float t0,
                       float t1) {
-    if (a.entry_res == 0 || !(t1 < __builtin_inff()) || !(t0 <= t1)) return 0;
+    // a segment longer than 8 finest voxels almost never fits one voxel deep
+    // enough to skip levels: start at the root without looking
+    if (a.entry_res == 0 || !((t1 - t0) * a.entry_inv <= 8.0f)) return 0;
     const int E = a.entry_res;
     int ia[3], ib[3];
     const float o[3] = {ox, oy, oz}, d[3] = {dx, dy, dz}, lo[3] = {a.entry_lo_x, a.entry_lo_y, a.entry_lo_z};
