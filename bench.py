@@ -17,6 +17,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -71,6 +72,16 @@ def measured_traffic(tau):
     if rec.get("source_sha256") != source_sha256() or rec.get("threshold") != tau:
         return None
     return rec["read_bytes"] + rec["write_bytes"]
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def artefacts(t, prim, o, d, t_ref, prim_ref, o_ref, h):
@@ -209,6 +220,10 @@ def main():
     # work counters at the chosen threshold -> algorithmic bytes per ray
     (_, _, _, _), cnt = hyb.trace_counters(bvh, sdf128, R, TMAX, tau, hyb.MODE_COMBINED)
     c = cnt.double().mean(dim=0).cpu().numpy()
+    cnt_np = cnt.cpu().numpy()
+    work = {name: {"mean": float(cnt_np[:, k].mean()), "p50": float(np.percentile(cnt_np[:, k], 50)),
+                   "p99": float(np.percentile(cnt_np[:, k], 99)), "max": int(cnt_np[:, k].max())}
+            for k, name in enumerate(("bvh_nodes", "triangles", "df_fetches"))}
     bytes_per_ray = 24 + 16 + 128 * c[0] + 48 * c[1] + 32 * c[2]
 
     # timed region: K steps of the combined query at the chosen threshold
@@ -244,7 +259,7 @@ def main():
             if el >= 10.0 or m >= n:
                 break
             m = int(min(n, max(2 * m, m * 15.0 / max(el, 1e-3))))
-        cpu = dict(value=sub.n / el / 1e6, unit="Mrays/s", cores=oracle.threads(), kind="oracle",
+        cpu = dict(value=sub.n / el / 1e6, unit="Mrays/s", cores=oracle.threads(), kind="oracle", cpu_model=cpu_model(),
                    sample="%d of the %d rays at a fixed stride over the tile-ordered G-buffer rays (%.1f s), "
                           "combined query at threshold %s in FP64: %s" % (
                               sub.n, n, el, chosen["tau"],
@@ -281,6 +296,7 @@ def main():
         "sweep": sweep,
         "target_artefact_rate": target,
         "speedup_vs_bvh_only": ms_bvh / ms_step,
+        "work_per_ray": work,
         "timed_wall_s": wall,
     }
     print(json.dumps(line), flush=True)
@@ -597,7 +613,7 @@ def bench_ao(args, torch, hyb, W, dev, stream):
     out = hyb.alloc_hits(n)
     o_np, d_np, ob_np = rays.o.astype(np.float64), rays.d.astype(np.float64), rb.o.astype(np.float64)
     res = []
-    for t_ao in (0.05, 0.1, 0.25, 0.5, 1.0):
+    for t_ao in (0.05, 0.1, 0.25, 0.5, 1.0, 2.0):
         ms_bvh = time_launches(lambda: hyb.trace_bvh(bvh, R, t_ao, out=out), stream, args.reps, 2)
         ref_t, ref_p = out[0].cpu().numpy().astype(np.float64), out[1].cpu().numpy()
         row = dict(t_ao=t_ao, t_ao_voxels=t_ao / h, triangles_ms=ms_bvh, occluded=float((ref_p != -1).mean()))
