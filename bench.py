@@ -355,6 +355,12 @@ def bench_precision(args, torch, hyb, W, dev, stream):
     t0 = time.time()
     og, n_nodes = oracle.sdf_grid_sparse(scene, g4, 256, sub.o, sub.d, TMAX, progress=log)
     log("oracle: exact samples at %d nodes (%.1fs)" % (n_nodes, time.time() - t0))
+    # the oracle above kept the GPU idle for a minute or more: bring it back to
+    # its working clocks before timing (about half a second of launches)
+    t0 = time.time()
+    while time.time() - t0 < 0.5:
+        hyb.trace(bvh, grids["f32"], R, TMAX, 0.0, out=out)
+        torch.cuda.synchronize()
     res = {}
     for tau in (0.0, 1.0):
         ref = oracle.query(scene.verts, scene.tris, og, g4, sub.soa(), TMAX, tau)
