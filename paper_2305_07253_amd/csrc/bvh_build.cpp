@@ -1,7 +1,9 @@
 // Binned-SAH BVH2 construction on the host (Wald, "On fast construction of
 // SAH-based bounding volume hierarchies", 2007: 32 bins per axis over the
-// centroid bounds), flattened into the 64-byte two-child node layout that the
-// device traversal reads with four 16-byte loads.
+// centroid bounds), flattened into 64-byte two-child nodes (read by the
+// distance-field build's nearest-triangle queries), collapsed into 128-byte
+// four-wide nodes that the trace traversal reads with seven 16-byte loads, and
+// the pyramid of traversal entry points.
 #include "bvh_build.hpp"
 
 #include <algorithm>
