@@ -132,7 +132,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the ray query shards by rays with no exchange step; "
-              "multi-GPU runs are not part of this build", file=sys.stderr)
+              "a multi-GPU job is one independent process per GPU on its share of the rays", file=sys.stderr)
         sys.exit(2)
 
     import torch
