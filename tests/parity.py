@@ -35,7 +35,8 @@ def check(got, ref, margin, cond, label="", max_excluded=0.05, uv_tol=UV_TOL):
             bad_prim.sum(), i.tolist(), prim[i].tolist(), rp[i].tolist(), t[i].tolist(), rt[i].tolist(),
             margin[i].tolist()))
     hit = dec & (rp != -1) & (prim == rp) & (cond >= COND)
-    err = np.abs(t.astype(np.float64) - rt)
+    with np.errstate(invalid="ignore"):  # misses: inf - inf
+        err = np.abs(t.astype(np.float64) - rt)
     tol = T_REL * np.maximum(rt, T_FLOOR)
     bad_t = hit & ~(err <= tol)
     if bad_t.any():
