@@ -22,11 +22,14 @@
  *    are asynchronous on `stream`; build calls return after their work on
  *    `stream` has completed.
  *  - The library owns handles until *_destroy.  Builders copy their inputs.  The
- *    caller owns ray and hit buffers; trace calls allocate nothing.
+ *    caller owns ray and hit buffers; trace calls allocate nothing (batches
+ *    allocate in hyb_batch_create and hyb_batch_tune, and build their graph on
+ *    the first launch after a change of launch shape).
  *  - Errors come back as a status, never as a crash or an exception.  A status
  *    other than HYB_OK leaves outputs unspecified.
- *  - Handles are immutable after build: concurrent trace calls on different
- *    streams are safe.
+ *  - BVH and distance-field handles are immutable after build: concurrent trace
+ *    calls on different streams are safe.  A batch handle is mutable (its
+ *    thresholds and launch shape): calls on one batch must be ordered.
  */
 #ifndef HYB_H
 #define HYB_H
