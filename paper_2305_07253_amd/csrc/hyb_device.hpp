@@ -452,8 +452,10 @@ struct DfRay {
     float qxf, qyf, qzf;
     float ix, iy, iz;   // time to cross one cell along each axis (inf if not moving)
     float t, b;         // current position and segment end
+    float cover;        // [start, cover] is verified free of roots
     int ci, cj, ck;     // current cell while walking
     bool walk;
+    bool relax;         // the next sphere step may be over-relaxed
     // a cell span [t, t + span] whose cubic k may vanish, left for df_resolve
     float k[4], span, t_exit;
     int axis;           // exit face of that cell: 0, 1, 2
@@ -464,6 +466,7 @@ enum DfStatus : int { kDfContinue = 0, kDfHit = 1, kDfMiss = 2, kDfSolve = 3 };
 // Moves to the neighbouring cell across the exit face `axis` at t_exit.
 HYB_HD int df_advance(const Grid& g, DfRay& r, int axis, float t_exit) {
     if (t_exit >= r.b) return kDfMiss;
+    r.cover = t_exit;  // the cell's span was checked
     if (axis == 0) r.ci += r.qxf > 0.0f ? 1 : -1;
     else if (axis == 1) r.cj += r.qyf > 0.0f ? 1 : -1;
     else r.ck += r.qzf > 0.0f ? 1 : -1;
@@ -502,10 +505,23 @@ HYB_HD bool df_init(const Grid& g, float ox, float oy, float oz, float dx, float
     r.iz = r.qzf != 0.0f ? approx_rcp(fabsf(r.qzf)) : __builtin_inff();
     r.t = a;
     r.b = b;
+    r.cover = a;
     r.ci = r.cj = r.ck = 0;
     r.walk = false;
+    r.relax = false;
     return true;
 }
+
+// Over-relaxed sphere steps (Keinert et al., "Enhanced Sphere Tracing", 2014):
+// a step of kOverRelax times the certified radius, kept only when the new
+// point's own certified interval reaches back to the end of the verified part
+// of the ray; otherwise the march returns there and steps plainly.  On the
+// GI-shaped workload this saves a tenth of the iterations (1.3 measured best
+// among 1.15 to 1.9), which pays for the extra bookkeeping only where a fetch
+// is dear: the I8 format (a load and eight block scales per fetch).
+constexpr float kOverRelax = 1.3f;
+template <int FMT>
+constexpr bool kRelaxes = FMT == kI8;
 
 // One iteration of the march: fetch the 8 corners of one cell, then either a
 // sphere step or a cell step (see df_first_root).  On kDfHit the hit is r.t;
@@ -524,11 +540,33 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     corners<FMT>(g, r.ci, r.cj, r.ck, f);
     if (COUNT) cnt.df++;
     const float val = lerp_cell(f, fx, fy, fz);
+    // no root within `safe` of this point (0 at or below the surface)
+    const float safe = val > 0.0f ? fmaxf(val * g.inv_l, val - g.two_e) : 0.0f;
+    if constexpr (kRelaxes<FMT>) {
+        if (r.t > r.cover && r.t - safe > r.cover) {
+            // an over-relaxed step left (cover, t - safe) unchecked: go back
+            r.t = r.cover;
+            r.walk = false;
+            r.relax = false;
+            return kDfContinue;
+        }
+    }
     if (val <= 0.0f) return kDfHit;
     if (val > (r.walk ? 2.0f * g.h : g.h)) {
         r.walk = false;
-        r.t += fmaxf(val * g.inv_l, val - g.two_e);
-        return r.t > r.b ? kDfMiss : kDfContinue;
+        if constexpr (kRelaxes<FMT>) {
+            r.cover = r.t + safe;
+            r.t += r.relax ? kOverRelax * safe : safe;
+            r.relax = true;
+            if (r.t > r.b) {
+                if (r.cover >= r.b) return kDfMiss;
+                r.t = r.b;
+            }
+            return kDfContinue;
+        } else {
+            r.t += safe;
+            return r.t > r.b ? kDfMiss : kDfContinue;
+        }
     }
     r.walk = true;
     // span of the ray inside the current cell, from the in-cell fractions
