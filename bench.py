@@ -360,18 +360,21 @@ def bench_precision(args, torch, hyb, W, dev, stream):
     t0 = time.time()
     og, n_nodes = oracle.sdf_grid_sparse(scene, g4, 256, sub.o, sub.d, TMAX, progress=log)
     log("oracle: exact samples at %d nodes (%.1fs)" % (n_nodes, time.time() - t0))
+    refs = {tau: oracle.query(scene.verts, scene.tris, og, g4, sub.soa(), TMAX, tau) for tau in (0.0, 1.0)}
+    for ref in refs.values():
+        assert np.all(np.isfinite(ref[0]) | (ref[1] == -1)), "oracle read a node outside the sampled cells"
     # the oracle above kept the GPU idle for a minute or more: bring it back to
-    # its working clocks before timing (about half a second of launches)
+    # its working clocks before timing (a second of launches; nothing but GPU
+    # work and the checks of its results runs between here and the last timing)
     t0 = time.time()
-    while time.time() - t0 < 0.5:
+    while time.time() - t0 < 1.0:
         hyb.trace(bvh, grids["f32"], R, TMAX, 0.0, out=out)
         torch.cuda.synchronize()
     res = {}
     for tau in (0.0, 1.0):
-        ref = oracle.query(scene.verts, scene.tris, og, g4, sub.soa(), TMAX, tau)
-        assert np.all(np.isfinite(ref[0]) | (ref[1] == -1)), "oracle read a node outside the sampled cells"
+        ref = refs[tau]
         for name, sdf in grids.items():
-            ms = time_launches(lambda: hyb.trace(bvh, sdf, R, TMAX, tau, out=out), stream, 10, 2)
+            ms = time_launches(lambda: hyb.trace(bvh, sdf, R, TMAX, tau, out=out), stream, 20, 3)
             t = out[0].cpu().numpy()[idx].astype(np.float64)
             prim = out[1].cpu().numpy()[idx]
             same = (prim == ref[1]) | ((prim >= 0) & (ref[1] >= 0))

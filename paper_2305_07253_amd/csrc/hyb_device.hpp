@@ -552,7 +552,7 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
         }
     }
     if (val <= 0.0f) return kDfHit;
-    if (val > (r.walk ? 2.0f * g.h : g.h)) {
+    if (val > g.h) {
         r.walk = false;
         if constexpr (kRelaxes<FMT>) {
             r.cover = r.t + safe;
@@ -610,10 +610,9 @@ HYB_HD int df_max_steps(const Grid& g) { return 16 * g.n + 64; }
 // Every iteration fetches the 8 corners of one cell and then takes one of two
 // steps, so lanes of a wavefront in different phases still execute the same
 // instruction stream:
-//   sphere step  g > band (h, or 2h once walking): advance by a distance the
-//                interpolant cannot cross, max(g / L, g - two_e) (the second
-//                bound only for grids that certify 1-Lipschitz samples,
-//                two_e = 2 (sqrt(3)/2 h + q));
+//   sphere step  g > h: advance by a distance the interpolant cannot cross,
+//                max(g / L, g - two_e) (the second bound only for grids that
+//                certify 1-Lipschitz samples, two_e = 2 (sqrt(3)/2 h + q));
 //   cell step    near the surface: the ray's span inside the current cell; a
 //                cell whose 8 corners are all positive holds no root (the
 //                interpolant is a convex blend of them), otherwise the exact
