@@ -154,15 +154,18 @@ hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t fl
  *   grid4   host, {lo_x, lo_y, lo_z, h}
  *   flags   0 or HYB_SDF_LIPSCHITZ_SAMPLES
  *   fmt     storage format the values are converted to
- * The Lipschitz bound used for safe steps is recomputed from the stored
- * (dequantized) values.
+ * The bounds used for safe steps (the Lipschitz bound and per-axis bounds of
+ * the partial derivatives) are recomputed from the stored (dequantized)
+ * values.
  * Errors: HYB_ERR_INVALID_ARG for NULL values/grid4/out, bad n, h <= 0,
  * non-finite grid4 or unknown flags. */
 hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4, uint32_t flags,
                              hyb_sdf_format fmt, void* stream, hyb_sdf* out);
 
 /* Grid placement, resolution and the Lipschitz bound L of the trilinear
- * interpolant of the stored samples (steps of g/L never pass a root). */
+ * interpolant of the stored samples (steps of g/L never pass a root; the
+ * trace kernels step by g / min(L, L_d) with L_d = max(1, sum_i s_i |d_i|)
+ * from per-axis slope bounds s_i, the ray's own bound). */
 hyb_status hyb_sdf_info(hyb_sdf sdf, float* grid4 /* host, 4 */, int32_t* n, float* lipschitz);
 
 /* Copy the samples as the trace kernels see them (dequantized for compact

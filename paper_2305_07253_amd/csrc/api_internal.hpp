@@ -34,6 +34,7 @@ struct hyb_sdf_s {
     int32_t n = 0, nb = 0;
     float grid4[4] = {0, 0, 0, 0};
     float lipschitz = 0.0f;
+    float slope[3] = {0, 0, 0};  // per-axis bounds of |df/dx_i|
     bool certified = false;  // samples are FP32 roundings of a 1-Lipschitz function
     hyb_sdf_format fmt = HYB_SDF_F32;
 };
@@ -63,23 +64,27 @@ inline bool valid_rays(const hyb_rays* r) {
 
 inline bool valid_hits(const hyb_hits* h) { return h && h->t && h->prim && h->u && h->v; }
 
-// Lipschitz bound of the stored grid: per-block maxima on the device, final
-// maximum on the host (build time; synchronous).
+// Lipschitz bound and per-axis slope bounds of the stored grid: per-block
+// maxima on the device, final maxima on the host (build time; synchronous).
 inline hyb_status compute_lipschitz(hyb_sdf_s* s, hipStream_t stream) {
     const int32_t nb = hyb::lipschitz_blocks(s->n);
     float* d_blocks = nullptr;
-    HYB_TRY(hipMalloc(&d_blocks, sizeof(float) * nb));
+    HYB_TRY(hipMalloc(&d_blocks, sizeof(float) * 4 * nb));
     int32_t got = 0;
     hipError_t e = hyb::launch_lipschitz(s->values, s->n, s->grid4[3], d_blocks, &got, stream);
-    std::vector<float> host(nb, 0.0f);
-    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), d_blocks, sizeof(float) * nb, hipMemcpyDeviceToHost, stream);
+    std::vector<float> host(4 * static_cast<size_t>(nb), 0.0f);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host.data(), d_blocks, sizeof(float) * 4 * nb, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     (void)hipFree(d_blocks);
     HYB_TRY(e);
-    float L = 0.0f;
-    for (float v : host) L = std::max(L, v);
-    if (!std::isfinite(L)) return HYB_ERR_INVALID_ARG;
-    s->lipschitz = hyb::finish_lipschitz(L);
+    float m[4] = {0, 0, 0, 0};
+    for (size_t b = 0; b < static_cast<size_t>(nb); ++b)
+        for (int c = 0; c < 4; ++c) m[c] = std::max(m[c], host[4 * b + c]);
+    for (float v : m)
+        if (!std::isfinite(v)) return HYB_ERR_INVALID_ARG;
+    s->lipschitz = hyb::finish_lipschitz(m[0]);
+    for (int c = 0; c < 3; ++c) s->slope[c] = hyb::finish_slope(m[1 + c]);
     return HYB_OK;
 }
 
@@ -143,6 +148,9 @@ inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s
         a.inv_h = 1.0f / s->grid4[3];
         a.inv_l = hyb::inv_step(s->lipschitz);
         a.two_e = (s->certified && s->fmt == HYB_SDF_F32) ? hyb::certified_slack(s->grid4[3], s->n) : __builtin_inff();
+        a.slope_x = s->slope[0];
+        a.slope_y = s->slope[1];
+        a.slope_z = s->slope[2];
     }
 }
 

@@ -242,6 +242,7 @@ struct Grid {
     float lo_x, lo_y, lo_z, h, inv_h;
     float inv_l;    // 1 / Lipschitz bound of the interpolant (slightly reduced)
     float two_e;    // 2 x (interpolation error bound + storage error), +inf if uncertified
+    float slope_x, slope_y, slope_z;  // bounds of |df/dx|, |df/dy|, |df/dz| over the grid
     double inv_hd;  // 1 / h in FP64
 };
 
@@ -327,35 +328,46 @@ HYB_HD void corners(const Grid& g, int i, int j, int k, float f[8]) {
     }
 }
 
-HYB_HD float lerp_cell(const float f[8], float x, float y, float z) {
-    const float a = f[0] + x * (f[1] - f[0]);
-    const float b = f[2] + x * (f[3] - f[2]);
-    const float c = f[4] + x * (f[5] - f[4]);
-    const float d = f[6] + x * (f[7] - f[6]);
-    const float e = a + y * (b - a);
-    const float q = c + y * (d - c);
-    return e + z * (q - e);
+// Trilinear interpolation inside one cell at in-cell fractions (x, y, z),
+// keeping the differences it forms: with them the cubic along a ray through
+// the point (cell_cubic) costs a few more operations.
+struct CellLerp {
+    float val;                // the interpolant at (x, y, z)
+    float dx0, dx1, dx2, dx3; // f1 - f0, f3 - f2, f5 - f4, f7 - f6: x-differences of the 4 x-edges
+    float dy0, dy1;           // y-differences of the x-lerps at z = 0 and z = 1
+    float dz;                 // z-difference of the y-lerps: df/dz at the point
+};
+
+HYB_HD CellLerp lerp_cell(const float f[8], float x, float y, float z) {
+    CellLerp L;
+    L.dx0 = f[1] - f[0];
+    L.dx1 = f[3] - f[2];
+    L.dx2 = f[5] - f[4];
+    L.dx3 = f[7] - f[6];
+    const float a = f[0] + x * L.dx0, b = f[2] + x * L.dx1;
+    const float c = f[4] + x * L.dx2, d = f[6] + x * L.dx3;
+    L.dy0 = b - a;
+    L.dy1 = d - c;
+    const float e = a + y * L.dy0, q = c + y * L.dy1;
+    L.dz = q - e;
+    L.val = e + z * L.dz;
+    return L;
 }
 
 // Cubic g(s) = k0 + k1 s + k2 s^2 + k3 s^3 of the trilinear interpolant along
-// (x + qx s, y + qy s, z + qz s) inside one cell, from its monomial form
-// f = c0 + cx x + cy y + cz z + cxy xy + cxz xz + cyz yz + cxyz xyz.
-HYB_HD void cell_cubic(const float f[8], float x, float y, float z, float qx, float qy, float qz,
-                                           float k[4]) {
-    const float c0 = f[0];
-    const float cx = f[1] - f[0], cy = f[2] - f[0], cz = f[4] - f[0];
-    const float cxy = f[3] - f[2] - f[1] + f[0];
-    const float cxz = f[5] - f[4] - f[1] + f[0];
-    const float cyz = f[6] - f[4] - f[2] + f[0];
-    const float cxyz = f[7] - f[6] - f[5] - f[3] + f[4] + f[2] + f[1] - f[0];
-    // gradient at s = 0 and mixed second-order terms
-    const float gx = cx + cxy * y + cxz * z + cxyz * y * z;
-    const float gy = cy + cxy * x + cyz * z + cxyz * x * z;
-    const float gz = cz + cxz * x + cyz * y + cxyz * x * y;
-    k[0] = c0 + cx * x + cy * y + cz * z + cxy * x * y + cxz * x * z + cyz * y * z + cxyz * x * y * z;
-    k[1] = gx * qx + gy * qy + gz * qz;
-    k[2] = qx * qy * (cxy + cxyz * z) + qx * qz * (cxz + cxyz * y) + qy * qz * (cyz + cxyz * x);
-    k[3] = cxyz * qx * qy * qz;
+// (x + qx s, y + qy s, z + qz s) inside one cell.  A trilinear function equals
+// its Taylor expansion about any point, f(p + u) = f + fx ux + fy uy + fz uz +
+// fxy ux uy + fxz ux uz + fyz uy uz + fxyz ux uy uz, and every partial
+// derivative at p is a lerp of differences formed by lerp_cell.
+HYB_HD void cell_cubic(const CellLerp& L, float y, float z, float qx, float qy, float qz, float k[4]) {
+    const float hx0 = L.dx1 - L.dx0, hx1 = L.dx3 - L.dx2;     // fxy at z = 0 and z = 1
+    const float gx0 = L.dx0 + y * hx0, gx1 = L.dx2 + y * hx1; // fx at z = 0 and z = 1
+    const float fxz = gx1 - gx0, fyz = L.dy1 - L.dy0, fxyz = hx1 - hx0;
+    const float fx = gx0 + z * fxz, fy = L.dy0 + z * fyz, fxy = hx0 + z * fxyz;
+    k[0] = L.val;
+    k[1] = fx * qx + fy * qy + L.dz * qz;
+    k[2] = fxy * (qx * qy) + fxz * (qx * qz) + fyz * (qy * qz);
+    k[3] = fxyz * (qx * qy) * qz;
 }
 
 HYB_HD float cubic_at(const float k[4], float s) { return fmaf(fmaf(fmaf(k[3], s, k[2]), s, k[1]), s, k[0]); }
@@ -450,7 +462,11 @@ struct DfRay {
     double px, py, pz;  // origin in cell units, (o - lo) / h
     double qx, qy, qz;  // direction in cell units, d / h
     float qxf, qyf, qzf;
-    float ix, iy, iz;   // time to cross one cell along each axis (inf if not moving)
+    float inv_l;        // sphere-step factor: 1 / bound of |d/dt f(o + t d)|
+    // time to the cell's exit face along each axis from in-cell fraction f is
+    // f m + e: with c the time to cross one cell, (1 - f) c moving up (m = -c,
+    // e = c), f c moving down (m = c, e = 0); c = inf when not moving
+    float mx, my, mz, ex, ey, ez;
     float t, b;         // current position and segment end
     float cover;        // [start, cover] is verified free of roots
     int ci, cj, ck;     // current cell while walking
@@ -500,9 +516,21 @@ HYB_HD bool df_init(const Grid& g, float ox, float oy, float oz, float dx, float
     r.qzf = (float)r.qz;
     // these only size the cell spans of the walk (a span a few ulps long or
     // short moves a cell boundary by as much, on a continuous interpolant)
-    r.ix = r.qxf != 0.0f ? approx_rcp(fabsf(r.qxf)) : __builtin_inff();
-    r.iy = r.qyf != 0.0f ? approx_rcp(fabsf(r.qyf)) : __builtin_inff();
-    r.iz = r.qzf != 0.0f ? approx_rcp(fabsf(r.qzf)) : __builtin_inff();
+    const float cx = r.qxf != 0.0f ? approx_rcp(fabsf(r.qxf)) : __builtin_inff();
+    const float cy = r.qyf != 0.0f ? approx_rcp(fabsf(r.qyf)) : __builtin_inff();
+    const float cz = r.qzf != 0.0f ? approx_rcp(fabsf(r.qzf)) : __builtin_inff();
+    r.mx = r.qxf > 0.0f ? -cx : cx;
+    r.my = r.qyf > 0.0f ? -cy : cy;
+    r.mz = r.qzf > 0.0f ? -cz : cz;
+    r.ex = r.qxf > 0.0f ? cx : 0.0f;
+    r.ey = r.qyf > 0.0f ? cy : 0.0f;
+    r.ez = r.qzf > 0.0f ? cz : 0.0f;
+    // the interpolant changes along the ray by at most sum |df/dx_i| |d_i| per
+    // unit t (at least 1 keeps steps finite on flat fields), often well below
+    // the gradient-norm bound L (1.5 against sqrt(3) for an exact distance
+    // field and a random direction); rounded down 2e-6 to stay a bound
+    const float ld = fmaf(g.slope_x, fabsf(dx), fmaf(g.slope_y, fabsf(dy), g.slope_z * fabsf(dz)));
+    r.inv_l = fmaxf(g.inv_l, approx_rcp(fmaxf(ld, 1.0f)) * (1.0f - 2e-6f));
     r.t = a;
     r.b = b;
     r.cover = a;
@@ -523,6 +551,14 @@ constexpr float kOverRelax = 1.3f;
 template <int FMT>
 constexpr bool kRelaxes = FMT == kI8;
 
+// Smallest of the samples' bit patterns read as signed integers: <= 0 exactly
+// when some sample is <= 0 (-0 included), for samples that are not NaN.
+HYB_HD int min_bits(const float f[8]) {
+    int m = __builtin_bit_cast(int, f[0]);
+    for (int c = 1; c < 8; ++c) m = min(m, __builtin_bit_cast(int, f[c]));
+    return m;
+}
+
 // One iteration of the march: fetch the 8 corners of one cell, then either a
 // sphere step or a cell step (see df_first_root).  On kDfHit the hit is r.t;
 // kDfSolve leaves a cell span that may hold the first root for df_resolve.
@@ -539,9 +575,10 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     float f[8];
     corners<FMT>(g, r.ci, r.cj, r.ck, f);
     if (COUNT) cnt.df++;
-    const float val = lerp_cell(f, fx, fy, fz);
+    const CellLerp L = lerp_cell(f, fx, fy, fz);
+    const float val = L.val;
     // no root within `safe` of this point (0 at or below the surface)
-    const float safe = val > 0.0f ? fmaxf(val * g.inv_l, val - g.two_e) : 0.0f;
+    const float safe = val > 0.0f ? fmaxf(val * r.inv_l, val - g.two_e) : 0.0f;
     if constexpr (kRelaxes<FMT>) {
         if (r.t > r.cover && r.t - safe > r.cover) {
             // an over-relaxed step left (cover, t - safe) unchecked: go back
@@ -570,15 +607,14 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     }
     r.walk = true;
     // span of the ray inside the current cell, from the in-cell fractions
-    const float ex = (r.qxf > 0.0f ? 1.0f - fx : fx) * r.ix;
-    const float ey = (r.qyf > 0.0f ? 1.0f - fy : fy) * r.iy;
-    const float ez = (r.qzf > 0.0f ? 1.0f - fz : fz) * r.iz;
+    const float ex = fmaf(fx, r.mx, r.ex);
+    const float ey = fmaf(fy, r.my, r.ey);
+    const float ez = fmaf(fz, r.mz, r.ez);
     const float t_exit = r.t + fmaxf(fminf(fminf(ex, ey), ez), 0.0f);
     const int axis = (ex <= ey && ex <= ez) ? 0 : (ey <= ez ? 1 : 2);
-    const float fmin = fminf(fminf(fminf(f[0], f[1]), fminf(f[2], f[3])), fminf(fminf(f[4], f[5]), fminf(f[6], f[7])));
-    if (fmin <= 0.0f) {
+    if (min_bits(f) <= 0) {
         // some corner at or below zero: the cell's cubic along the ray
-        cell_cubic(f, fx, fy, fz, r.qxf, r.qyf, r.qzf, r.k);
+        cell_cubic(L, fy, fz, r.qxf, r.qyf, r.qzf, r.k);
         r.span = fminf(t_exit, r.b) - r.t;
         if (cubic_may_vanish(r.k, r.span)) {
             r.t_exit = t_exit;
@@ -611,8 +647,9 @@ HYB_HD int df_max_steps(const Grid& g) { return 16 * g.n + 64; }
 // steps, so lanes of a wavefront in different phases still execute the same
 // instruction stream:
 //   sphere step  g > h: advance by a distance the interpolant cannot cross,
-//                max(g / L, g - two_e) (the second bound only for grids that
-//                certify 1-Lipschitz samples, two_e = 2 (sqrt(3)/2 h + q));
+//                max(g / L_d, g - two_e) with L_d the ray's own slope bound
+//                (df_init; the second bound only for grids that certify
+//                1-Lipschitz samples, two_e = 2 (sqrt(3)/2 h + q));
 //   cell step    near the surface: the ray's span inside the current cell; a
 //                cell whose 8 corners are all positive holds no root (the
 //                interpolant is a convex blend of them), otherwise the exact
@@ -678,6 +715,15 @@ HYB_HD bool df_hit_gradient(const Grid& g, float ox, float oy, float oz, float d
 // Gradient bound of the trilinear interpolant inside one cell (corners f):
 // each partial derivative is a convex blend of the cell's four edge differences
 // along that axis (divided by h), so |grad| <= sqrt(mx^2 + my^2 + mz^2) / h.
+// Largest |edge difference| / h of a cell along x, y and z: bounds of
+// |df/dx|, |df/dy|, |df/dz| inside it (each partial derivative of the
+// interpolant is a blend of the edge differences along its axis).
+HYB_HD void cell_slopes(const float f[8], float inv_h, float m[3]) {
+    m[0] = fmaxf(fmaxf(fabsf(f[1] - f[0]), fabsf(f[3] - f[2])), fmaxf(fabsf(f[5] - f[4]), fabsf(f[7] - f[6]))) * inv_h;
+    m[1] = fmaxf(fmaxf(fabsf(f[2] - f[0]), fabsf(f[3] - f[1])), fmaxf(fabsf(f[6] - f[4]), fabsf(f[7] - f[5]))) * inv_h;
+    m[2] = fmaxf(fmaxf(fabsf(f[4] - f[0]), fabsf(f[5] - f[1])), fmaxf(fabsf(f[6] - f[2]), fabsf(f[7] - f[3]))) * inv_h;
+}
+
 HYB_HD float cell_lipschitz(const float f[8], float inv_h) {
     const float mx = fmaxf(fmaxf(fabsf(f[1] - f[0]), fabsf(f[3] - f[2])), fmaxf(fabsf(f[5] - f[4]), fabsf(f[7] - f[6])));
     const float my = fmaxf(fmaxf(fabsf(f[2] - f[0]), fabsf(f[3] - f[1])), fmaxf(fabsf(f[6] - f[4]), fabsf(f[7] - f[5])));
@@ -689,6 +735,9 @@ HYB_HD float cell_lipschitz(const float f[8], float inv_h) {
 // least 1 (keeps steps finite on flat fields), rounded up a few ulps so it
 // stays a bound after FP32 evaluation.
 inline float finish_lipschitz(float cell_max) { return fmaxf(cell_max, 1.0f) * (1.0f + 4e-7f); }
+
+// Per-axis slope bound from the largest cell value, rounded up likewise.
+inline float finish_slope(float cell_max) { return cell_max * (1.0f + 4e-7f); }
 
 // Reciprocal step factor: g * inv_step(L) is a safe sphere-tracing step.
 inline float inv_step(float lipschitz) { return (1.0f / lipschitz) * (1.0f - 1e-6f); }
@@ -753,7 +802,7 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
     hit.v = 0.0f;
     if (tmin <= tmax) {
         const Grid g = {a.sdf, a.scales, a.n_grid, a.nb, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e,
-                        1.0 / (double)a.h};
+                        a.slope_x, a.slope_y, a.slope_z, 1.0 / (double)a.h};
         if (MODE == kBvhOnly) {
             hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, tmax, stack, stride, cnt,
                                                  entry_node(a, ox, oy, oz, dx, dy, dz, tmin, tmax));

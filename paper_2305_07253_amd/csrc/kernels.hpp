@@ -28,6 +28,7 @@ struct TraceArgs {
     int32_t n_grid, nb;
     float lo_x, lo_y, lo_z, h, inv_h, inv_l;
     float two_e;  // certified-grid step slack (+inf: use g / L only)
+    float slope_x, slope_y, slope_z;  // per-axis bounds of the interpolant's partial derivatives
     // query
     float tmax, tau, tau_end;
     int64_t n;
@@ -88,8 +89,9 @@ struct SdfBuildArgs {
 
 hipError_t launch_sdf_build(const SdfBuildArgs& a, hipStream_t stream);
 
-// Per-block maxima of the cell Lipschitz bounds of an n^3 grid (x fastest)
-// into block_max[0 .. n_blocks); returns n_blocks through *n_blocks.
+// Per-block maxima of the cell Lipschitz bounds and of the per-axis cell
+// slopes of an n^3 grid (x fastest): block b writes block_max[4 b .. 4 b + 4)
+// = (Lipschitz, slope x, slope y, slope z); returns n_blocks through *n_blocks.
 hipError_t launch_lipschitz(const float* grid, int32_t n, float h, float* block_max, int32_t* n_blocks,
                             hipStream_t stream);
 int32_t lipschitz_blocks(int32_t n);

@@ -18,26 +18,31 @@ __global__ __launch_bounds__(256) void k_sdf_build(SdfBuildArgs a) {
     a.out[id] = (float)sdf_node_value(a.nodes, a.tris, p, a.exterior_solid);
 }
 
-// Largest cell gradient bound of the grid (cell_lipschitz), one value per block.
+// Largest cell gradient bound of the grid (cell_lipschitz) and largest
+// per-axis slopes (cell_slopes): 4 values per block.
 __global__ __launch_bounds__(256) void k_lipschitz(const float* __restrict__ g, int32_t n, float inv_h,
                                                    float* __restrict__ block_max) {
-    __shared__ float red[256];
+    __shared__ float red[4][256];
     const int64_t m = n - 1;
-    float best = 0.0f;
+    float best[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < m * m * m; c += (int64_t)gridDim.x * 256) {
         const int64_t i = c % m, j = (c / m) % m, k = c / (m * m);
         const float* p = g + i + (int64_t)n * (j + (int64_t)n * k);
         const int64_t sy = n, sz = (int64_t)n * n;
         const float f[8] = {p[0], p[1], p[sy], p[sy + 1], p[sz], p[sz + 1], p[sz + sy], p[sz + sy + 1]};
-        best = fmaxf(best, cell_lipschitz(f, inv_h));
+        float s[3];
+        cell_slopes(f, inv_h, s);
+        best[0] = fmaxf(best[0], cell_lipschitz(f, inv_h));
+        for (int a = 0; a < 3; ++a) best[1 + a] = fmaxf(best[1 + a], s[a]);
     }
-    red[threadIdx.x] = best;
+    for (int a = 0; a < 4; ++a) red[a][threadIdx.x] = best[a];
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        if (threadIdx.x < s)
+            for (int a = 0; a < 4; ++a) red[a][threadIdx.x] = fmaxf(red[a][threadIdx.x], red[a][threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) block_max[blockIdx.x] = red[0];
+    if (threadIdx.x < 4) block_max[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // I8 block scales: one thread per 8^3 block of nodes, max |f| / 127.

@@ -86,7 +86,7 @@ int main(int argc, char** argv) {
         fclose(o);
         return 0;
     }
-    float L = 0.0f;
+    float L = 0.0f, slope[3] = {0.0f, 0.0f, 0.0f};
     const float inv_h = 1.0f / par[5];
     for (long long k = 0; k + 1 < N; ++k)
         for (long long j = 0; j + 1 < N; ++j)
@@ -94,8 +94,12 @@ int main(int argc, char** argv) {
                 const float* p = grid.data() + i + N * (j + N * k);
                 const float c[8] = {p[0], p[1], p[N], p[N + 1], p[N * N], p[N * N + 1], p[N * N + N], p[N * N + N + 1]};
                 L = fmaxf(L, hyb::cell_lipschitz(c, inv_h));
+                float s[3];
+                hyb::cell_slopes(c, inv_h, s);
+                for (int a = 0; a < 3; ++a) slope[a] = fmaxf(slope[a], s[a]);
             }
     L = hyb::finish_lipschitz(L);
+    for (int a = 0; a < 3; ++a) slope[a] = hyb::finish_slope(slope[a]);
 
     // the kernels read the samples in the format's bricked layout (exact-size
     // buffers, so the sanitizer sees any read past the storage); the FP32
@@ -142,12 +146,15 @@ int main(int argc, char** argv) {
     a.lo_x = par[2]; a.lo_y = par[3]; a.lo_z = par[4]; a.h = par[5]; a.inv_h = inv_h;
     a.inv_l = hyb::inv_step(L);
     a.two_e = (par[6] != 0.0f && fmt == 0) ? hyb::certified_slack(par[5], (int)N) : __builtin_inff();
+    a.slope_x = slope[0];
+    a.slope_y = slope[1];
+    a.slope_z = slope[2];
     a.tmax = par[0];
     a.tau = par[1];
     a.n = n;
     if (what == 2) {
         const hyb::Grid g = {b32.data(), nullptr, (int)N, 0, par[2], par[3], par[4], par[5], inv_h, a.inv_l,
-                             __builtin_inff(), 1.0 / (double)par[5]};
+                             __builtin_inff(), a.slope_x, a.slope_y, a.slope_z, 1.0 / (double)par[5]};
         std::vector<long long> nodes(8 * n, -1);
         std::vector<float> dts(8 * n, 0.0f);
         for (long long i = 0; i < n; ++i) {
