@@ -75,11 +75,15 @@ typedef enum {
     HYB_SDF_I8_BRICK = 2
 } hyb_sdf_format;
 
-/* Rays: device SoA arrays of n floats each.  d must be unit length (the
+/* Rays: device SoA arrays of n floats each, n <= HYB_MAX_RAYS per call (the
+ * trace kernels run one ray per work item and a launch counts its work items
+ * in 32 bits).  d must be unit length (the
  * distance-field steps assume it).  tmin may be NULL (tmin = 0 for every ray).
  * tmax may be NULL (every ray uses the call's scalar tmax); otherwise ray i
  * ends at min(tmax[i], scalar tmax) (shadow rays end at their light sample).
  * A ray with tmin > tmax is reported as a miss. */
+#define HYB_MAX_RAYS 2147483647LL
+
 typedef struct {
     const float *ox, *oy, *oz;
     const float *dx, *dy, *dz;
@@ -178,7 +182,7 @@ hyb_status hyb_sdf_read(hyb_sdf sdf, float* out, void* stream);
  *   tmax       0 <= tmax, may be +inf
  *   threshold  0 <= threshold, in voxels of the grid, may be +inf
  * n == 0 is a no-op.  Errors: HYB_ERR_INVALID_ARG for NULL handles/pointers,
- * n < 0, NaN or negative tmax/threshold. */
+ * n < 0 or n > HYB_MAX_RAYS, NaN or negative tmax/threshold. */
 hyb_status hyb_trace(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, float threshold,
                      hyb_hits* hits, void* stream);
 
@@ -226,8 +230,8 @@ hyb_status hyb_trace_counters(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, in
  *   grad_grid      device, n_grid^3 floats (x fastest): accumulated into (+=)
  * The sdf must be FP32 (HYB_SDF_F32).  Accumulation uses float atomics: sums
  * agree across runs up to FP32 rounding of the order of additions.
- * Errors: HYB_ERR_INVALID_ARG for NULL pointers, n < 0, NaN/negative tmax;
- * HYB_ERR_UNSUPPORTED for a compact-format sdf. */
+ * Errors: HYB_ERR_INVALID_ARG for NULL pointers, n < 0 or n > HYB_MAX_RAYS,
+ * NaN/negative tmax; HYB_ERR_UNSUPPORTED for a compact-format sdf. */
 hyb_status hyb_df_backward(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, const float* t_hit,
                            const float* grad_t, float* grad_grid, void* stream);
 

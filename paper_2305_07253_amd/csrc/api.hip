@@ -244,7 +244,7 @@ hyb_status hyb_trace_shadow(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int6
 
 hyb_status hyb_df_backward(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, const float* t_hit,
                            const float* grad_t, float* grad_grid, void* stream) {
-    if (!sdf || n < 0 || std::isnan(tmax) || tmax < 0.0f) return HYB_ERR_INVALID_ARG;
+    if (!sdf || n < 0 || n > HYB_MAX_RAYS || std::isnan(tmax) || tmax < 0.0f) return HYB_ERR_INVALID_ARG;
     if (n == 0) return HYB_OK;
     if (!valid_rays(rays) || !t_hit || !grad_t || !grad_grid) return HYB_ERR_INVALID_ARG;
     if (sdf->fmt != HYB_SDF_F32) return HYB_ERR_UNSUPPORTED;

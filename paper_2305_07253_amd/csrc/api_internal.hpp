@@ -155,7 +155,7 @@ inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s
 }
 
 inline hyb_status check_query(const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits) {
-    if (n < 0 || std::isnan(tmax) || tmax < 0.0f) return HYB_ERR_INVALID_ARG;
+    if (n < 0 || n > HYB_MAX_RAYS || std::isnan(tmax) || tmax < 0.0f) return HYB_ERR_INVALID_ARG;
     if (n > 0 && (!valid_rays(rays) || !valid_hits(hits))) return HYB_ERR_INVALID_ARG;
     return HYB_OK;
 }

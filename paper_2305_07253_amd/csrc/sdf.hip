@@ -59,14 +59,11 @@ __global__ __launch_bounds__(256) void k_block_scales(const float* __restrict__ 
     scales[b] = m > 0.0f ? m / 127.0f : 1.0f;
 }
 
-// Per-node conversion to F16 or I8 and the dequantized FP32 value.
 // One storage slot of the bricked layout: the sample of its node in the
 // storage format (0 for padding slots).
 template <int FMT>
-__global__ __launch_bounds__(256) void k_store(const float* __restrict__ in, int32_t n, int32_t nb, int64_t slots,
-                                               void* __restrict__ out, const float* __restrict__ scales) {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= slots) return;
+__device__ void store_slot(const float* __restrict__ in, int32_t n, int32_t nb, int64_t s, void* __restrict__ out,
+                           const float* __restrict__ scales) {
     int i, j, k;
     const bool node = Brick<FMT>::slot_node(s, n, i, j, k);
     const float f = node ? in[(int64_t)i + (int64_t)n * ((int64_t)j + (int64_t)n * k)] : 0.0f;
@@ -82,6 +79,16 @@ __global__ __launch_bounds__(256) void k_store(const float* __restrict__ in, int
         }
         static_cast<int8_t*>(out)[s] = (int8_t)q;
     }
+}
+
+// Every storage slot, in a grid-stride loop: the compact formats of a 1024^3
+// grid have 8.6e9 slots, more work items than a launch can count (32 bits per
+// dimension).
+template <int FMT>
+__global__ __launch_bounds__(256) void k_store(const float* __restrict__ in, int32_t n, int32_t nb, int64_t slots,
+                                               void* __restrict__ out, const float* __restrict__ scales) {
+    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < slots; s += (int64_t)gridDim.x * 256)
+        store_slot<FMT>(in, n, nb, s, out, scales);
 }
 
 // The dequantized FP32 value of every node, in place (linear order).
@@ -107,7 +114,7 @@ hipError_t launch_quantize(int fmt, float* values, int32_t n, void* out, float* 
     const int64_t total = (int64_t)n * n * n;
     const unsigned blocks = (unsigned)((total + 255) / 256);
     const int64_t slots = brick_storage(fmt, n);
-    const unsigned sblocks = (unsigned)((slots + 255) / 256);
+    const unsigned sblocks = (unsigned)std::min<int64_t>((slots + 255) / 256, int64_t(1) << 20);
     const int32_t nb = (n + kScaleBlock - 1) / kScaleBlock;
     if (fmt == kF32) {
         hipLaunchKernelGGL(k_store<kF32>, dim3(sblocks), dim3(256), 0, stream, values, n, nb, slots, out, scales);

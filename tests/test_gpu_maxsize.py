@@ -1,0 +1,90 @@
+"""GPU parity at the largest grid the API accepts (n = 1024), where the bricked
+stores pass 2^32 elements (I8, F16) or 2^32 bytes (FP32): every address above
+that must be formed in 64 bits.
+
+The field is the exact FP32 signed distance to a sphere (centre 0.5, radius
+0.3) on the nodes i h, h = 2^-10.  Rays start near the sphere's top (node
+k ~ 819, far into the upper half of every store) and are short enough that each
+segment stays inside a 160^3-node window aligned to the 8^3 scale blocks; the
+oracle gets that window of the same FP32 samples (dequantized by its own rule
+for F16 and I8), so its first root equals the one on the full grid.
+"""
+import numpy as np
+import pytest
+
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+N = 1024
+H = 2.0 ** -10
+CENTRE, RADIUS = 0.5, 0.3
+TMAX = 0.045
+WIN = (744, 432, 432)  # window start, nodes (k, j, i); multiples of 8
+WSIZE = 160
+
+
+@pytest.fixture(scope="module")
+def hyb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2305_07253_amd as hyb
+    hyb.lib()
+    return hyb
+
+
+@pytest.fixture(scope="module")
+def sphere_grid():
+    print("building the 1024^3 sphere field", flush=True)
+    x = np.arange(N, dtype=np.float64) * H - CENTRE
+    g = np.empty((N, N, N), dtype=np.float32)
+    yy = (x * x)[:, None] + (x * x)[None, :]
+    for k in range(N):
+        g[k] = (np.sqrt(yy + x[k] * x[k]) - RADIUS).astype(np.float32)
+    return g
+
+
+@pytest.fixture(scope="module")
+def rays():
+    rng = np.random.default_rng(23)
+    n = 4096
+    # origins 4-20 voxels above the surface within 4 degrees of the top
+    th = np.deg2rad(4.0) * np.sqrt(rng.uniform(0, 1, n))
+    ph = rng.uniform(0, 2 * np.pi, n)
+    u = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1)
+    o = CENTRE + (RADIUS + rng.uniform(4, 20, n)[:, None] * H) * u
+    # towards the centre, spread so that some rays graze or miss
+    d = -u + rng.normal(0, 1.0, (n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    soa = np.ascontiguousarray(np.concatenate([o.T, d.T]), dtype=np.float32)
+    # every segment inside the window, two cells from its faces
+    lo = np.array(WIN[::-1], dtype=np.float64) * H + 2 * H
+    hi = (np.array(WIN[::-1], dtype=np.float64) + WSIZE - 1) * H - 2 * H
+    for t in (0.0, TMAX):
+        p = soa[:3].T.astype(np.float64) + t * soa[3:].T.astype(np.float64)
+        assert np.all((p >= lo) & (p <= hi))
+    return soa
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_max_grid_size_parity(hyb, orc, sphere_grid, rays, fmt):
+    import torch
+    print("format", fmt, flush=True)
+    values = torch.from_numpy(sphere_grid.reshape(-1)).cuda()
+    sdf = hyb.sdf_from_grid(values, np.array([0.0, 0.0, 0.0, H], dtype=np.float32), fmt=fmt)
+    del values
+    got = [x.cpu().numpy() for x in hyb.trace_df(sdf, torch.from_numpy(rays).cuda(), TMAX)]
+    del sdf
+    torch.cuda.empty_cache()
+    k0, j0, i0 = WIN
+    win = np.ascontiguousarray(sphere_grid[k0:k0 + WSIZE, j0:j0 + WSIZE, i0:i0 + WSIZE])
+    if fmt:
+        win = orc.quantize(win, fmt)[0]
+    g4 = np.array([i0 * H, j0 * H, k0 * H, H], dtype=np.float32)
+    ref = orc.query(None, np.zeros((0, 3)), win, g4, rays, TMAX, 0.0, mode=orc.MODE_DF)
+    m, c = orc.margin(None, np.zeros((0, 3)), win, g4, rays, TMAX, 0.0, mode=orc.MODE_DF)
+    hits = (ref[1] == -2).mean()
+    assert 0.5 < hits < 0.9, hits
+    st = parity.check(got, ref, m, c, label="n=1024 fmt %d" % fmt)
+    print("n=1024 fmt", fmt, "hits %.3f" % hits, st)

@@ -135,6 +135,19 @@ def test_edge_arguments(hyb, orc, tiny, tiny_dev):
         parity.check(got, ref, m, c, label="tmin tmax=%s" % tmax, max_excluded=0.1)
     got = host(hyb.trace(tiny_dev["bvh"], tiny_dev["sdf"], to_dev(r.soa()), 2.0, 1.0, tmin=to_dev(tmin)))
     assert np.all(got[1][tmin > 2.0] == -1)
+    # more rays than one call takes (HYB_MAX_RAYS = 2^31 - 1): rejected before
+    # anything is read, so small buffers stand in
+    import ctypes
+    R = to_dev(r.soa())
+    rs, _ = hyb._rays_struct(R, None)
+    out = hyb.alloc_hits(r.n)
+    hs = hyb._hits_struct(out, r.n)
+    for fn, args in (("hyb_trace", (tiny_dev["bvh"].handle, tiny_dev["sdf"].handle)),
+                     ("hyb_trace_bvh", (tiny_dev["bvh"].handle,)), ("hyb_trace_df", (tiny_dev["sdf"].handle,))):
+        extra = (ctypes.c_float(1.0),) if fn == "hyb_trace" else ()
+        st = getattr(hyb.lib(), fn)(*args, ctypes.byref(rs), ctypes.c_int64(2 ** 31), ctypes.c_float(1.0), *extra,
+                                    ctypes.byref(hs), None)
+        assert st == 1, (fn, st)  # HYB_ERR_INVALID_ARG
 
 
 def test_empty_and_degenerate_meshes(hyb, orc):
