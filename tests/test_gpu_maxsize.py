@@ -88,3 +88,26 @@ def test_max_grid_size_parity(hyb, orc, sphere_grid, rays, fmt):
     assert 0.5 < hits < 0.9, hits
     st = parity.check(got, ref, m, c, label="n=1024 fmt %d" % fmt)
     print("n=1024 fmt", fmt, "hits %.3f" % hits, st)
+
+
+def test_max_grid_size_sdf_build(hyb, orc, tiny):
+    """hyb_build_sdf at n = 1024 (FP32, 3.6e9 store slots): 4,096 random nodes,
+    the first and the last 256 included, within one FP32 ulp of the oracle's
+    exact signed distances, signs equal away from the surface."""
+    import torch
+    from paper_2305_07253_amd import workloads as W
+    sc = tiny["scene"]
+    g4 = W.room_grid(N)
+    print("building the 1024^3 grid of the tiny room", flush=True)
+    sdf = hyb.build_sdf(hyb.build_bvh(sc.verts, sc.tris), N, g4)
+    rng = np.random.default_rng(29)
+    idx = np.concatenate([np.arange(256), N ** 3 - 256 + np.arange(256), rng.integers(0, N ** 3, 3584)])
+    got = hyb.sdf_read(sdf).reshape(-1)[torch.from_numpy(idx).cuda()].cpu().numpy()
+    del sdf
+    torch.cuda.empty_cache()
+    ref = orc.sdf_nodes(sc, g4, N, nodes=idx)
+    ulp = np.maximum(np.spacing(np.abs(ref).astype(np.float32)), 1e-15)
+    bad = np.abs(got.astype(np.float64) - ref) > ulp
+    assert bad.sum() == 0, (bad.sum(), idx[bad][:5], got[bad][:5], ref[bad][:5])
+    far = np.abs(ref) > 1e-6
+    assert np.array_equal(np.sign(got[far]), np.sign(ref[far]))
