@@ -574,8 +574,10 @@ def bench_batch(args, torch, hyb, W, dev, stream):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "bytes_per_ray": total_bytes / n_rays},
         "steps": args.steps, "timed_wall_s": wall,
+        "scenes": [{"triangles": m["tris"], "rays": m["rays"], "grid": m["grid"],
+                    "threshold": None if math.isinf(taus[k]) else taus[k], "error_rate": float(err[k])}
+                   for k, m in enumerate(meta)],
     }
-
 
 
 def bench_shadow(args, torch, hyb, W, dev, stream):
