@@ -29,7 +29,6 @@ struct Counters {
     int nodes = 0, tris = 0, df = 0;
 };
 
-HYB_HD float bits_f(int v) { return __builtin_bit_cast(float, v); }
 HYB_HD int bits_i(float v) { return __builtin_bit_cast(int, v); }
 
 HYB_HD float pick3(float a, float b, float c, int k) { return k == 0 ? a : (k == 1 ? b : c); }
@@ -451,10 +450,6 @@ HYB_HD float cubic_first_root(const float k[4], float S) {
         return -1.0f;
     }
     return refine_root(k, lo, hi, 1e-6f * S);
-}
-
-HYB_HD float cell_first_root(const float k[4], float S) {
-    return cubic_may_vanish(k, S) ? cubic_first_root(k, S) : -1.0f;
 }
 
 // Marching state of one ray (see df_first_root).
