@@ -279,7 +279,8 @@ typedef struct {
 #define HYB_TUNE_LAUNCH 2u    /* choose the launch shape */
 
 typedef struct {
-    const float* thresholds; /* host, candidate thresholds (>= 0, +inf allowed); NULL: 0, 0.5, 1, 2, 4, +inf */
+    const float* thresholds; /* host, candidate thresholds (>= 0, +inf allowed);
+                                NULL: 0, 0.5, 1, 2, 4, 8, 16, 32, +inf */
     int32_t n_thresholds;    /* 0 with thresholds == NULL */
     float max_error_rate;    /* per item: fraction of its rays allowed to differ from the triangles-only result */
     int32_t reps;            /* timed launches per candidate, 1..100 */

@@ -435,7 +435,7 @@ hyb_status hyb_batch_tune(hyb_batch batch, const hyb_batch_tune_opts* opts, floa
     if (opts->n_thresholds > 0) {
         cands.assign(opts->thresholds, opts->thresholds + opts->n_thresholds);
     } else {
-        cands = {0.0f, 0.5f, 1.0f, 2.0f, 4.0f, __builtin_inff()};
+        cands = {0.0f, 0.5f, 1.0f, 2.0f, 4.0f, 8.0f, 16.0f, 32.0f, __builtin_inff()};
     }
     for (float c : cands)
         if (std::isnan(c) || c < 0.0f) return HYB_ERR_INVALID_ARG;
