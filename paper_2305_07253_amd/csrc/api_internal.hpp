@@ -98,7 +98,8 @@ inline hyb_status quantize(hyb_sdf_s* s, hipStream_t stream) {
     s->nb = (s->n + hyb::kScaleBlock - 1) / hyb::kScaleBlock;
     HYB_TRY(hipMalloc(&s->store, count * elem));
     if (s->fmt == HYB_SDF_I8_BRICK)
-        HYB_TRY(hipMalloc(&s->scales, sizeof(float) * static_cast<size_t>(s->nb) * s->nb * s->nb));
+        // one float of padding: the trace kernels load x-adjacent scales in pairs
+        HYB_TRY(hipMalloc(&s->scales, sizeof(float) * (static_cast<size_t>(s->nb) * s->nb * s->nb + 1)));
     return from_hip(hyb::launch_quantize(fmt, s->values, s->n, s->store, s->scales, stream));
 }
 

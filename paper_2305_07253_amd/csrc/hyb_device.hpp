@@ -318,11 +318,16 @@ HYB_HD void corners(const Grid& g, int i, int j, int k, float f[8]) {
         const uint32_t bi0 = (uint32_t)i / kScaleBlock, bi1 = (uint32_t)(i + 1) / kScaleBlock;
         const uint32_t bj0 = (uint32_t)j / kScaleBlock, bj1 = (uint32_t)(j + 1) / kScaleBlock;
         const uint32_t bk0 = (uint32_t)k / kScaleBlock, bk1 = (uint32_t)(k + 1) / kScaleBlock;
-        const char* sp = reinterpret_cast<const char*>(g.scales);
-        for (int c = 0; c < 8; ++c) {
-            const uint32_t bi = (c & 1) ? bi1 : bi0, bj = (c & 2) ? bj1 : bj0, bk = (c & 4) ? bk1 : bk0;
-            const float scale = *reinterpret_cast<const float*>(sp + ((bi + nb * (bj + nb * bk)) << 2));
-            f[c] = (float)p[off[c]] * scale;
+        // the scales of x-adjacent blocks are adjacent: one pair per (y, z) of
+        // the corners, the second taken when the cell crosses an x block face
+        // (the table holds one float of padding past the last block)
+        const bool cross_x = bi1 != bi0;
+        for (int c = 0; c < 8; c += 2) {
+            const uint32_t bj = (c & 2) ? bj1 : bj0, bk = (c & 4) ? bk1 : bk0;
+            const float* sp = g.scales + (bi0 + nb * (bj + nb * bk));
+            const float s0 = sp[0], s1 = sp[1];
+            f[c] = (float)p[off[c]] * s0;
+            f[c + 1] = (float)p[off[c + 1]] * (cross_x ? s1 : s0);
         }
     }
 }

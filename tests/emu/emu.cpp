@@ -51,6 +51,7 @@ int main(int argc, char** argv) {
     std::vector<_Float16> g16 = what == 0 && N > 0 && fmt == 1 ? rd<_Float16>(f, N * N * N) : std::vector<_Float16>();
     std::vector<int8_t> g8 = what == 0 && N > 0 && fmt == 2 ? rd<int8_t>(f, N * N * N) : std::vector<int8_t>();
     std::vector<float> scales = what == 0 && N > 0 && fmt == 2 ? rd<float>(f, nb * nb * nb) : std::vector<float>();
+    if (!scales.empty()) scales.push_back(0.0f);  // the padding float the library allocates
     auto rays = rd<float>(f, 6 * n);
     auto tmin = (has_tmin & 1) ? rd<float>(f, n) : std::vector<float>();
     auto tmaxr = (has_tmin & 2) ? rd<float>(f, n) : std::vector<float>();
