@@ -627,7 +627,9 @@ HYB_HD int df_resolve(const Grid& g, DfRay& r) {
 }
 
 // Upper bound on the iterations of one march: sphere steps are at least
-// h / L >= h / sqrt(3) long and cell steps enter a new cell along the ray.
+// h / L >= h / sqrt(3) long (an over-relaxed step the next iteration takes
+// back is followed by a plain one), cell steps enter a new cell along the ray,
+// and the clipped segment is at most sqrt(3) (n - 1) h long.
 HYB_HD int df_max_steps(const Grid& g) { return 16 * g.n + 64; }
 
 // First t in [a, b] (clipped to the grid box) where the trilinear interpolant
@@ -639,14 +641,16 @@ HYB_HD int df_max_steps(const Grid& g) { return 16 * g.n + 64; }
 //   sphere step  g > h: advance by a distance the interpolant cannot cross,
 //                max(g / L_d, g - two_e) with L_d the ray's own slope bound
 //                (df_init; the second bound only for grids that certify
-//                1-Lipschitz samples, two_e = 2 (sqrt(3)/2 h + q));
+//                1-Lipschitz samples, two_e = 2 (sqrt(3)/2 h + q)), times
+//                kOverRelax after a plain step;
 //   cell step    near the surface: the ray's span inside the current cell; a
 //                cell whose 8 corners are all positive holds no root (the
 //                interpolant is a convex blend of them), otherwise the exact
 //                first root of the cell's cubic; then the next cell in DDA order.
 // The ray's position in cell units, X(t) = (o - lo)/h + t d/h, is formed in
-// FP64 (MI355X runs FP64 FMA at half the FP32 rate) so the in-cell fraction
-// keeps full FP32 precision tens of cells from the origin.
+// FP64 (on MI355X an FP64 FMA issues at the rate of an unpacked FP32 one) so
+// the in-cell fraction keeps full FP32 precision tens of cells from the
+// origin.
 template <int FMT, bool COUNT>
 HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz, float a,
                            float b, Counters& cnt) {
