@@ -445,11 +445,15 @@ def bench_diff(args, torch, hyb, W, dev, stream):
     before = artefact_rate(theta0, Rh, target_h)
     theta = theta0.clone().requires_grad_(True)
     opt = torch.optim.Adam([theta], lr=args.lr_scale * h)
-    # time forward + backward (+ Adam) per step
+    # wall clock per step (forward, backward, Adam, loss read back), timed from
+    # step 10 on: the first steps also load torch's and Adam's kernels
     losses = []
-    torch.cuda.synchronize()
+    skip = min(10, args.adam_steps // 2)
     t0 = time.time()
     for it in range(args.adam_steps):
+        if it == skip:
+            torch.cuda.synchronize()
+            t0 = time.time()
         opt.zero_grad()
         loss = loss_of(theta)
         loss.backward()
@@ -458,7 +462,7 @@ def bench_diff(args, torch, hyb, W, dev, stream):
         if it % 50 == 0:
             log("adam step %d loss %.3e" % (it, losses[-1]))
     torch.cuda.synchronize()
-    step_ms = (time.time() - t0) * 1e3 / max(args.adam_steps, 1)
+    step_ms = (time.time() - t0) * 1e3 / max(args.adam_steps - skip, 1)
     after = artefact_rate(theta, Rh, target_h)
     # kernel times of one forward and one backward on the final grid
     sdf = hyb.sdf_from_grid(theta.detach().contiguous(), g4)
@@ -467,6 +471,13 @@ def bench_diff(args, torch, hyb, W, dev, stream):
     grad = torch.zeros(128 ** 3, device=dev)
     ones = torch.ones(rays.n, device=dev)
     ms_bwd = time_launches(lambda: hyb.df_backward(sdf, R, TMAX, out[0], ones, grad), stream, 20, 2)
+    x = theta.detach().contiguous()
+    torch.cuda.synchronize()
+    t1 = time.time()
+    for _ in range(20):
+        hyb.sdf_from_grid(x, g4)
+    torch.cuda.synchronize()
+    ms_upload = (time.time() - t1) * 1e3 / 20
     log("refit: loss %.3e -> %.3e; artefacts %.4f -> %.4f; step %.2f ms" % (losses[0], losses[-1], before[0],
                                                                             after[0], step_ms))
     return {"config": "differentiation", "workload": "GI scene (%d triangles), 128^3 FP32 learnable grid, "
@@ -477,7 +488,8 @@ def bench_diff(args, torch, hyb, W, dev, stream):
             "loss_first": losses[0] if losses else None, "loss_last": losses[-1] if losses else None,
             "heldout_artefact_rate_before": before[0], "heldout_artefact_rate_after": after[0],
             "heldout_mean_dt_over_h_before": before[1], "heldout_mean_dt_over_h_after": after[1],
-            "ms_per_adam_step": step_ms, "forward_kernel_ms": ms_fwd, "backward_kernel_ms": ms_bwd,
+            "ms_per_adam_step": step_ms, "adam_steps_timed": args.adam_steps - skip, "forward_kernel_ms": ms_fwd,
+            "backward_kernel_ms": ms_bwd, "sdf_from_grid_ms": ms_upload,
             "forward_mrays_s": rays.n / ms_fwd / 1e3, "backward_mrays_s": rays.n / ms_bwd / 1e3}
 
 
