@@ -10,7 +10,9 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_df_backward(TraceArgs a, const float* __restrict__ t_hit,
                                                      const float* __restrict__ grad_t, float* __restrict__ grad_grid) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // every ray costs about the same here: one contiguous eighth of the rays
+    // per die keeps the atomics of neighbouring hits in one L2
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x, max(gridDim.x / kXcds, 1u)) * 256 + threadIdx.x;
     if (i >= a.n) return;
     const float gt = grad_t[i];
     if (gt == 0.0f) return;

@@ -13,7 +13,7 @@ namespace hyb {
 template <int MODE, int FMT, bool COUNT>
 __global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a) {
     extern __shared__ int s_stack[];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x, kXcdRun) * kBlock + threadIdx.x;
     if (i >= a.n) return;
     trace_ray<MODE, FMT, COUNT>(a, i, s_stack + threadIdx.x, kBlock);
 }

@@ -15,6 +15,8 @@
 //         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays], tmax f32[n_rays]
 // what 0 (trace): output t f32[n], prim i32[n], u f32[n], v f32[n], counts i32[3n]
 // what 1 (sdf):   output f32[N^3] signed distances of the grid nodes
+// what 3 (block order): hdr[1] = blocks nb, hdr[4] = run; output u32[nb], the
+//                 block each workgroup of a trace launch processes
 // what 2 (grad):  input as what 0 plus t_hit f32[n_rays] after the ray arrays;
 //                 output per ray i64[8] node indices (-1: no contribution) and
 //                 f32[8] d t / d sample
@@ -42,6 +44,16 @@ int main(int argc, char** argv) {
     if (!f) return 2;
     auto hdr = rd<long long>(f, 8);
     auto par = rd<float>(f, 8);
+    if (hdr[0] == 3) {
+        fclose(f);
+        const uint32_t nb = (uint32_t)hdr[1], run = (uint32_t)hdr[4];
+        std::vector<uint32_t> order(nb);
+        for (uint32_t b = 0; b < nb; ++b) order[b] = hyb::xcd_block(b, nb, run);
+        FILE* o = fopen(argv[2], "wb");
+        if (!o || fwrite(order.data(), sizeof(uint32_t), nb, o) != nb) return 2;
+        fclose(o);
+        return 0;
+    }
     const long long what = hdr[0], n = hdr[1], nv = hdr[2], nt = hdr[3], N = hdr[4], has_tmin = hdr[5], mode = hdr[6];
     const int fmt = (int)hdr[7];
     const long long nb = (N + hyb::kScaleBlock - 1) / hyb::kScaleBlock;

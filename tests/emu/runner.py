@@ -113,3 +113,9 @@ def df_grad(grid, grid4, rays_soa, t_hit, tmax, tmin=None):
     par = [tmax, 0, g4[0], g4[1], g4[2], g4[3], 0, 0]
     raw = _run(hdr, par, arrays, 64 * n + 32 * n)
     return raw[:64 * n].view(np.int64).reshape(n, 8), raw[64 * n:].view(np.float32).reshape(n, 8)
+
+
+def block_order(nb: int, run: int):
+    """The kernels' workgroup-to-block map (xcd_block) for a launch of nb blocks."""
+    raw = _run([3, nb, 0, 0, run, 0, 0, 0], [0] * 8, [], 4 * nb)
+    return raw.view(np.uint32)

@@ -184,3 +184,28 @@ def test_grid_sizes_with_partial_bricks(emu, orc, tiny, n):
             ref = orc.query(sc.verts, sc.tris, deq, g4, rays, 2.0, tau)
             m, c = orc.margin(sc.verts, sc.tris, deq, g4, rays, 2.0, tau)
             parity.check(got, ref, m, c, label="emu n=%d fmt %d tau %s" % (n, fmt, tau))
+
+
+@pytest.mark.parametrize("run", [1, 16, 100])
+def test_block_order_is_a_permutation(emu, run):
+    """The trace kernels' workgroup-to-block map: every block of a launch is
+    processed exactly once, and within each full group of 8 * run blocks the
+    workgroups of one die (b mod 8) take `run` consecutive blocks in turn."""
+    for nb in (1, 7, 8, 9, 127, 128, 129, 8100, 24 * run + 5):
+        order = runner.block_order(nb, run).astype(np.int64)
+        assert np.array_equal(np.sort(order), np.arange(nb)), nb
+        full = nb // (8 * run) * (8 * run)
+        assert np.array_equal(order[full:], np.arange(full, nb))
+        for x in range(8):
+            runs = order[x:full:8].reshape(-1, run)
+            assert np.all(np.diff(runs, axis=1) == 1) and np.all(runs[:, 0] % run == 0), (nb, x)
+
+
+def test_block_order_eighths(emu):
+    """run = nb / 8 (the backward kernel's choice): each die gets one
+    contiguous eighth of the blocks, the remainder keeps its place."""
+    for nb in (8, 64, 4099, 8100):
+        order = runner.block_order(nb, nb // 8).astype(np.int64)
+        for x in range(8):
+            mine = order[x:nb // 8 * 8:8]
+            assert np.array_equal(mine, np.arange(x * (nb // 8), (x + 1) * (nb // 8)))
