@@ -400,7 +400,7 @@ def bench_precision(args, torch, hyb, W, dev, stream):
                 name, tau, ms, rays.n / ms / 1e3, same.mean(), rel.mean(), np.percentile(rel, 99)))
     return {"config": "precision", "workload": "%d-triangle room, 256^3 grid (h=1/251), %d rays (4 per pixel, "
             "1920x1080 G-buffer), tmax 0.5" % (scene.n_tris, rays.n), "oracle_sample": int(len(idx)),
-            "kernel_store_bytes": {"f32": 4 * 27 * 128 ** 3, "f16": 2 * 8 * 255 ** 3, "i8": 8 * 255 ** 3 + 4 * 32 ** 3},
+            "kernel_store_bytes": {"f32": 4 * 32 * 128 ** 3, "f16": 2 * 8 * 255 ** 3, "i8": 8 * 255 ** 3 + 4 * 32 ** 3},
             "linear_fp32_bytes": 4 * 256 ** 3,
             "results": res}
 

@@ -65,10 +65,10 @@ typedef struct hyb_sdf_s* hyb_sdf; /* distance-field grid; library-owned device 
  * Compact formats do not use the certified-sample step bound.  Inside the
  * library the kernels read a bricked copy in which every cell's 8 corner
  * samples lie together (bricks of 2^3 cells with their 3^3 nodes for F32,
- * 27 samples per 8 cells; one cell with its 8 nodes for F16 and I8), so the
- * device memory of a grid is n^3 FP32 values plus that copy.  Every interface
- * that takes or returns grid values (hyb_sdf_from_grid, hyb_sdf_read,
- * hyb_df_backward) uses the linear n^3 order, x fastest. */
+ * padded to 32 samples per 8 cells; one cell with its 8 nodes for F16 and
+ * I8), so the device memory of a grid is n^3 FP32 values plus that copy.
+ * Every interface that takes or returns grid values (hyb_sdf_from_grid,
+ * hyb_sdf_read, hyb_df_backward) uses the linear n^3 order, x fastest. */
 typedef enum {
     HYB_SDF_F32 = 0,
     HYB_SDF_F16 = 1,

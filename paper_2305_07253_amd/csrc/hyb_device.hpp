@@ -276,7 +276,9 @@ struct Grid {
 // fixed offsets from one address: a fetch is a few wide loads with immediate
 // offsets inside one or two cache lines, and the nodes around a ray share
 // lines.  C per format (fastest measured on the GI-shaped workload):
-//   F32: C = 2, 27 samples per 8 cells (3.4x the n^3 samples), a fetch spans 56 B
+//   F32: C = 2, the 27 samples of a brick padded to 32 (4x the n^3 samples):
+//        each brick is one 128-byte cache line, so a fetch touches exactly one
+//        (unpadded, 43% of the 56-byte fetches straddled two)
 //   F16, I8: C = 1, the 8 corners of each cell contiguous (16 / 8 B, one load)
 // Slots of nodes beyond the grid are padding and never read.
 template <int FMT>
@@ -284,12 +286,13 @@ struct Brick {
     static constexpr int kCells = FMT == kF32 ? 2 : 1;
     static constexpr int kSide = kCells + 1;
     static constexpr int kNodes = kSide * kSide * kSide;
+    static constexpr int kStride = FMT == kF32 ? 32 : kNodes;  // slots per brick (padding at the end)
 
     HYB_HD static int per_axis(int n) { return (n - 1 + kCells - 1) / kCells; }
 
     HYB_HD static int64_t storage(int n) {
         const int64_t b = per_axis(n);
-        return b * b * b * kNodes;
+        return b * b * b * kStride;
     }
 
     // Storage slot of corner 0 (the node (i, j, k)) of cell (i, j, k); cells
@@ -300,14 +303,18 @@ struct Brick {
         const uint32_t bi = ui / kCells, bj = uj / kCells, bk = uk / kCells;
         const uint32_t r = (ui - bi * kCells) + kSide * ((uj - bj * kCells) + kSide * (uk - bk * kCells));
         const uint32_t brick = (bk * nb + bj) * nb + bi;
-        return (int64_t)((uint64_t)brick * (uint32_t)kNodes + r);
+        return (int64_t)((uint64_t)brick * (uint32_t)kStride + r);
     }
 
     // The node stored in slot s; false for a padding slot.
     HYB_HD static bool slot_node(int64_t s, int n, int& i, int& j, int& k) {
         const int nbk = per_axis(n);
-        const int64_t b = s / kNodes;
-        const int r = (int)(s - b * kNodes);
+        const int64_t b = s / kStride;
+        const int r = (int)(s - b * kStride);
+        if (r >= kNodes) {
+            i = j = k = 0;
+            return false;
+        }
         const int bi = (int)(b % nbk), bj = (int)((b / nbk) % nbk), bk = (int)(b / ((int64_t)nbk * nbk));
         i = bi * kCells + r % kSide;
         j = bj * kCells + (r / kSide) % kSide;

@@ -91,7 +91,7 @@ def test_max_grid_size_parity(hyb, orc, sphere_grid, rays, fmt):
 
 
 def test_max_grid_size_sdf_build(hyb, orc, tiny):
-    """hyb_build_sdf at n = 1024 (FP32, 3.6e9 store slots): 4,096 random nodes,
+    """hyb_build_sdf at n = 1024 (FP32, 4.3e9 store slots): 4,096 random nodes,
     the first and the last 256 included, within one FP32 ulp of the oracle's
     exact signed distances, signs equal away from the surface."""
     import torch
