@@ -37,6 +37,7 @@ struct hyb_sdf_s {
     float slope[3] = {0, 0, 0};  // per-axis bounds of |df/dx_i|
     bool certified = false;  // samples are FP32 roundings of a 1-Lipschitz function
     hyb_sdf_format fmt = HYB_SDF_F32;
+    int32_t layout = 0;  // the kernels' storage format and brick layout (hyb::SdfFormat)
 };
 
 namespace hyb_api {
@@ -92,7 +93,8 @@ inline hyb_status compute_lipschitz(hyb_sdf_s* s, hipStream_t stream) {
 // bricked layout); for the compact formats the dequantized values replace
 // s->values in place.
 inline hyb_status quantize(hyb_sdf_s* s, hipStream_t stream) {
-    const int fmt = s->fmt == HYB_SDF_F32 ? hyb::kF32 : (s->fmt == HYB_SDF_F16 ? hyb::kF16 : hyb::kI8);
+    const int fmt = s->fmt == HYB_SDF_F32 ? hyb::kF32 : (s->fmt == HYB_SDF_F16 ? hyb::f16_layout(s->n) : hyb::kI8);
+    s->layout = fmt;
     const size_t count = static_cast<size_t>(hyb::brick_storage(fmt, s->n));
     const size_t elem = s->fmt == HYB_SDF_F32 ? 4 : (s->fmt == HYB_SDF_F16 ? 2 : 1);
     s->nb = (s->n + hyb::kScaleBlock - 1) / hyb::kScaleBlock;
@@ -139,7 +141,7 @@ inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s
     if (s) {
         a.sdf = s->store;
         a.scales = s->scales;
-        a.fmt = static_cast<int32_t>(s->fmt);
+        a.fmt = s->layout;
         a.nb = s->nb;
         a.n_grid = s->n;
         a.lo_x = s->grid4[0];

@@ -52,7 +52,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FMT == k
         const int64_t base = (int64_t)(w - b.item_start[lo]) * b.rays_per_item;
         for (int k = 0; k < b.rays_per_item; k += kWave) {
             const int64_t i = base + k + lane;
-            if (i < a.n) trace_ray<kCombined, FMT, false, LDS>(a, i, s_stack + threadIdx.x, kBlock);
+            if (i >= a.n) continue;
+            // F16 scenes may differ in brick layout (a.fmt is the same for
+            // the whole wavefront)
+            if (FMT == kF16 && a.fmt == kF16B2)
+                trace_ray<kCombined, kF16B2, false, LDS>(a, i, s_stack + threadIdx.x, kBlock);
+            else
+                trace_ray<kCombined, FMT, false, LDS>(a, i, s_stack + threadIdx.x, kBlock);
         }
     }
 }

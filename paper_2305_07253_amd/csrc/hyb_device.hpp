@@ -253,7 +253,10 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
 // distance field
 // ---------------------------------------------------------------------------
 
-enum SdfFormat : int { kF32 = 0, kF16 = 1, kI8 = 2 };
+// Storage format and brick layout of the kernels' copy: kF16B2 is F16 in the
+// bricks of 2^3 cells that FP32 uses, for grids whose one-cell F16 copy would
+// crowd the 256 MB MALL (f16_layout).
+enum SdfFormat : int { kF32 = 0, kF16 = 1, kI8 = 2, kF16B2 = 3 };
 constexpr int kScaleBlock = 8;  // I8: one scale per 8^3 block of nodes
 
 struct Grid {
@@ -280,13 +283,15 @@ struct Grid {
 //        each brick is one 128-byte cache line, so a fetch touches exactly one
 //        (unpadded, 43% of the 56-byte fetches straddled two)
 //   F16, I8: C = 1, the 8 corners of each cell contiguous (16 / 8 B, one load)
+//   F16 of large grids (kF16B2): C = 2, 27 halves padded to 32 (64 B): half
+//        the footprint of one-cell bricks, eight 2-byte loads per fetch
 // Slots of nodes beyond the grid are padding and never read.
 template <int FMT>
 struct Brick {
-    static constexpr int kCells = FMT == kF32 ? 2 : 1;
+    static constexpr int kCells = FMT == kF32 || FMT == kF16B2 ? 2 : 1;
     static constexpr int kSide = kCells + 1;
     static constexpr int kNodes = kSide * kSide * kSide;
-    static constexpr int kStride = FMT == kF32 ? 32 : kNodes;  // slots per brick (padding at the end)
+    static constexpr int kStride = kCells == 2 ? 32 : kNodes;  // slots per brick (padding at the end)
 
     HYB_HD static int per_axis(int n) { return (n - 1 + kCells - 1) / kCells; }
 
@@ -325,7 +330,21 @@ struct Brick {
 
 // Slots of the bricked storage of an n^3 grid in format fmt (runtime format).
 inline int64_t brick_storage(int fmt, int n) {
-    return fmt == kF32 ? Brick<kF32>::storage(n) : (fmt == kF16 ? Brick<kF16>::storage(n) : Brick<kI8>::storage(n));
+    switch (fmt) {
+        case kF32: return Brick<kF32>::storage(n);
+        case kF16: return Brick<kF16>::storage(n);
+        case kF16B2: return Brick<kF16B2>::storage(n);
+        default: return Brick<kI8>::storage(n);
+    }
+}
+
+// Kernel layout of an F16 grid of n^3 samples: two-cell bricks once the
+// one-cell copy ((n - 1)^3 cells of 16 B) passes 128 MiB, half the MALL.
+// Measured: at 128^3 (33 MB) one-cell bricks are 6% faster on the GI rays, at
+// 256^3 (265 MB) two-cell bricks 20% faster.
+inline int f16_layout(int n) {
+    const int64_t c = n - 1;
+    return c * c * c * 16 > (int64_t(128) << 20) ? kF16B2 : kF16;
 }
 
 // The 8 samples of cell (i, j, k), corner c = (i + (c & 1), j + (c >> 1 & 1), k + (c >> 2)).
@@ -338,7 +357,7 @@ HYB_HD void corners(const Grid& g, int i, int j, int k, float f[8]) {
     if constexpr (FMT == kF32) {
         const float* p = static_cast<const float*>(g.v) + slot;
         for (int c = 0; c < 8; ++c) f[c] = p[off[c]];
-    } else if constexpr (FMT == kF16) {
+    } else if constexpr (FMT == kF16 || FMT == kF16B2) {
         const _Float16* p = static_cast<const _Float16*>(g.v) + slot;
         for (int c = 0; c < 8; ++c) f[c] = (float)p[off[c]];
     } else {

@@ -69,7 +69,7 @@ __device__ void store_slot(const float* __restrict__ in, int32_t n, int32_t nb, 
     const float f = node ? in[(int64_t)i + (int64_t)n * ((int64_t)j + (int64_t)n * k)] : 0.0f;
     if constexpr (FMT == kF32) {
         static_cast<float*>(out)[s] = f;
-    } else if constexpr (FMT == kF16) {
+    } else if constexpr (FMT == kF16 || FMT == kF16B2) {
         static_cast<_Float16*>(out)[s] = (_Float16)f;
     } else {
         float q = 0.0f;
@@ -120,6 +120,9 @@ hipError_t launch_quantize(int fmt, float* values, int32_t n, void* out, float* 
         hipLaunchKernelGGL(k_store<kF32>, dim3(sblocks), dim3(256), 0, stream, values, n, nb, slots, out, scales);
     } else if (fmt == kF16) {
         hipLaunchKernelGGL(k_store<kF16>, dim3(sblocks), dim3(256), 0, stream, values, n, nb, slots, out, scales);
+        hipLaunchKernelGGL(k_dequantize<kF16>, dim3(blocks), dim3(256), 0, stream, values, n, nb, scales);
+    } else if (fmt == kF16B2) {
+        hipLaunchKernelGGL(k_store<kF16B2>, dim3(sblocks), dim3(256), 0, stream, values, n, nb, slots, out, scales);
         hipLaunchKernelGGL(k_dequantize<kF16>, dim3(blocks), dim3(256), 0, stream, values, n, nb, scales);
     } else if (fmt == kI8) {
         const int64_t nbb = (int64_t)nb * nb * nb;

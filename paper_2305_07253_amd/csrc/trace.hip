@@ -32,6 +32,7 @@ static hipError_t launch_fmt(const TraceArgs& a, hipStream_t stream) {
     switch (a.fmt) {
         case kF32: return launch<MODE, kF32, COUNT>(a, stream);
         case kF16: return launch<MODE, kF16, COUNT>(a, stream);
+        case kF16B2: return launch<MODE, kF16B2, COUNT>(a, stream);
         case kI8: return launch<MODE, kI8, COUNT>(a, stream);
         default: return hipErrorInvalidValue;
     }

@@ -10,7 +10,8 @@
 //         flag: exterior solid (what 1) / certified 1-Lipschitz samples (what 0)
 //         verts f32[3 n_verts], tris i32[3 n_tris],
 //         grid (what 0, N > 0): f32[N^3] dequantized values, then the stored
-//           values (f16 or i8 [N^3]) and f32 block scales [nb^3] for fmt 1/2,
+//           values (f16 or i8 [N^3]) and f32 block scales [nb^3] for fmt 1/2
+//           (fmt 3: the f16 values laid out in the two-cell bricks of large grids),
 //           all x fastest (the emulator lays them out in bricks),
 //         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays], tmax f32[n_rays]
 // what 0 (trace): output t f32[n], prim i32[n], u f32[n], v f32[n], counts i32[3n]
@@ -60,7 +61,7 @@ int main(int argc, char** argv) {
     auto verts = rd<float>(f, 3 * nv);
     auto tris = rd<int32_t>(f, 3 * nt);
     std::vector<float> grid = what != 1 && N > 0 ? rd<float>(f, N * N * N) : std::vector<float>();
-    std::vector<_Float16> g16 = what == 0 && N > 0 && fmt == 1 ? rd<_Float16>(f, N * N * N) : std::vector<_Float16>();
+    std::vector<_Float16> g16 = what == 0 && N > 0 && (fmt == 1 || fmt == 3) ? rd<_Float16>(f, N * N * N) : std::vector<_Float16>();
     std::vector<int8_t> g8 = what == 0 && N > 0 && fmt == 2 ? rd<int8_t>(f, N * N * N) : std::vector<int8_t>();
     std::vector<float> scales = what == 0 && N > 0 && fmt == 2 ? rd<float>(f, nb * nb * nb) : std::vector<float>();
     if (!scales.empty()) scales.push_back(0.0f);  // the padding float the library allocates
@@ -118,7 +119,8 @@ int main(int argc, char** argv) {
     // buffers, so the sanitizer sees any read past the storage); the FP32
     // copy also serves the backward body
     const size_t n32 = N > 0 ? (size_t)hyb::Brick<hyb::kF32>::storage((int)N) : 0;
-    const size_t n16 = N > 0 ? (size_t)hyb::Brick<hyb::kF16>::storage((int)N) : 0;
+    const size_t n16 = N > 0 ? (size_t)(fmt == 3 ? hyb::Brick<hyb::kF16B2>::storage((int)N)
+                                                 : hyb::Brick<hyb::kF16>::storage((int)N)) : 0;
     const size_t n8 = N > 0 ? (size_t)hyb::Brick<hyb::kI8>::storage((int)N) : 0;
     std::vector<float> b32(grid.empty() ? 0 : n32, 0.0f);
     std::vector<_Float16> b16(g16.empty() ? 0 : n16, (_Float16)0.0f);
@@ -127,7 +129,9 @@ int main(int argc, char** argv) {
     for (size_t s = 0; s < b32.size(); ++s)
         if (hyb::Brick<hyb::kF32>::slot_node((int64_t)s, (int)N, i, j, k)) b32[s] = grid.at(i + N * (j + N * (long long)k));
     for (size_t s = 0; s < b16.size(); ++s)
-        if (hyb::Brick<hyb::kF16>::slot_node((int64_t)s, (int)N, i, j, k)) b16[s] = g16.at(i + N * (j + N * (long long)k));
+        if (fmt == 3 ? hyb::Brick<hyb::kF16B2>::slot_node((int64_t)s, (int)N, i, j, k)
+                     : hyb::Brick<hyb::kF16>::slot_node((int64_t)s, (int)N, i, j, k))
+            b16[s] = g16.at(i + N * (j + N * (long long)k));
     for (size_t s = 0; s < b8.size(); ++s)
         if (hyb::Brick<hyb::kI8>::slot_node((int64_t)s, (int)N, i, j, k)) b8[s] = g8.at(i + N * (j + N * (long long)k));
 
@@ -150,7 +154,7 @@ int main(int argc, char** argv) {
     a.entry_levels = bvh.entry_levels;
     a.tris = tri4.data();
     a.sdf = grid.empty() ? nullptr
-            : (fmt == 1 ? static_cast<const void*>(b16.data())
+            : (fmt == 1 || fmt == 3 ? static_cast<const void*>(b16.data())
                         : (fmt == 2 ? static_cast<const void*>(b8.data()) : static_cast<const void*>(b32.data())));
     a.scales = scales.empty() ? nullptr : scales.data();
     a.fmt = fmt;
@@ -190,6 +194,9 @@ int main(int argc, char** argv) {
         else if (fmt == 1) {
             if (mode == 0) hyb::trace_ray<hyb::kCombined, hyb::kF16, true>(a, i, stack.data(), 1);
             else hyb::trace_ray<hyb::kDfOnly, hyb::kF16, true>(a, i, stack.data(), 1);
+        } else if (fmt == 3) {
+            if (mode == 0) hyb::trace_ray<hyb::kCombined, hyb::kF16B2, true>(a, i, stack.data(), 1);
+            else hyb::trace_ray<hyb::kDfOnly, hyb::kF16B2, true>(a, i, stack.data(), 1);
         } else if (fmt == 2) {
             if (mode == 0) hyb::trace_ray<hyb::kCombined, hyb::kI8, true>(a, i, stack.data(), 1);
             else hyb::trace_ray<hyb::kDfOnly, hyb::kI8, true>(a, i, stack.data(), 1);

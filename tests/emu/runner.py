@@ -59,7 +59,8 @@ def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, cert
     """Returns (t, prim, u, v, counts) exactly as the kernels compute them;
     `certified` marks the grid samples as exact distances; `fmt` stores the
     FP32 grid as F16 (1) or I8 with block scales (2), quantized by the
-    oracle's definition of the formats."""
+    oracle's definition of the formats; 3 is F16 in the kernels' two-cell
+    bricks of large grids."""
     rays_soa = np.ascontiguousarray(rays_soa, dtype=np.float32)
     n = rays_soa.shape[1]
     N = 0 if grid is None else np.asarray(grid).shape[-1]
@@ -67,9 +68,9 @@ def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, cert
     arrays = [np.asarray(verts, np.float32), np.asarray(tris, np.int32)]
     if N:
         import oracle
-        deq, stored, scales = oracle.quantize(np.asarray(grid, np.float32), fmt)
+        deq, stored, scales = oracle.quantize(np.asarray(grid, np.float32), 1 if fmt == 3 else fmt)
         arrays.append(deq)
-        if fmt == 1:
+        if fmt in (1, 3):
             arrays.append(stored.astype(np.float16))
         elif fmt == 2:
             arrays.append(stored.astype(np.int8))

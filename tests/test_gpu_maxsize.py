@@ -1,6 +1,7 @@
-"""GPU parity at the largest grid the API accepts (n = 1024), where the bricked
-stores pass 2^32 elements (I8, F16) or 2^32 bytes (FP32): every address above
-that must be formed in 64 bits.
+"""GPU parity at the largest grid the API accepts (n = 1024), where every
+bricked store passes 2^32 bytes and the I8 one 2^32 elements (F16 at this size
+is kept in two-cell bricks): every address above that must be formed in 64
+bits.
 
 The field is the exact FP32 signed distance to a sphere (centre 0.5, radius
 0.3) on the nodes i h, h = 2^-10.  Rays start near the sphere's top (node

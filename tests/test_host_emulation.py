@@ -30,13 +30,14 @@ def test_combined_matches_oracle(emu, orc, tiny, which, tau, certified):
     parity.check(got, ref, m, c, label="emu %s tau=%s certified=%s" % (which, tau, certified))
 
 
-@pytest.mark.parametrize("fmt", [1, 2])
+@pytest.mark.parametrize("fmt", [1, 2, 3])
 @pytest.mark.parametrize("tau", [0.0, 1.0, 4.0])
 def test_compact_formats_match_oracle(emu, orc, tiny, fmt, tau):
     """F16 and I8 grids: the kernels interpolate the dequantized values, which
-    the oracle computes by the same definition."""
+    the oracle computes by the same definition (3: F16 in the two-cell bricks
+    the library uses for large grids)."""
     sc, g4 = tiny["scene"], tiny["grid4"]
-    deq, _, _ = orc.quantize(tiny["grid"], fmt)
+    deq, _, _ = orc.quantize(tiny["grid"], 1 if fmt == 3 else fmt)
     for rays in (tiny["free"], tiny["surf"]):
         got = emu.trace(sc.verts, sc.tris, tiny["grid"], g4, rays.soa(), 2.0, tau, fmt=fmt)
         ref = orc.query(sc.verts, sc.tris, deq, g4, rays.soa(), 2.0, tau)
@@ -177,8 +178,8 @@ def test_grid_sizes_with_partial_bricks(emu, orc, tiny, n):
     g4 = W.room_grid(n)
     grid = orc.sdf_grid(sc, g4, n)
     rays = tiny["free"].soa()[:, :1024]
-    for fmt in (0, 1, 2):
-        deq = orc.quantize(grid, fmt)[0] if fmt else grid
+    for fmt in (0, 1, 2, 3):
+        deq = orc.quantize(grid, 1 if fmt == 3 else fmt)[0] if fmt else grid
         for tau in (0.0, 1.0):
             got = emu.trace(sc.verts, sc.tris, grid, g4, rays, 2.0, tau, fmt=fmt)
             ref = orc.query(sc.verts, sc.tris, deq, g4, rays, 2.0, tau)
