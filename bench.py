@@ -432,8 +432,8 @@ def bench_diff(args, torch, hyb, W, dev, stream):
 
     goal = torch.where(torch.isfinite(target), target, torch.full_like(target, TMAX))
 
-    def loss_of(theta):
-        t = df_hit(theta, g4, R, TMAX)
+    def loss_of(theta, grid=None):
+        t = df_hit(theta, g4, R, TMAX, sdf=grid)
         if args.loss == "both":
             use = torch.isfinite(t) & torch.isfinite(target)
             d = torch.where(use, t - target, torch.zeros_like(t))
@@ -443,26 +443,34 @@ def bench_diff(args, torch, hyb, W, dev, stream):
         return (d * d).sum() / use.sum().clamp(min=1)
 
     before = artefact_rate(theta0, Rh, target_h)
+
+    def run(theta, steps, grid, losses):
+        """Adam steps; wall clock per step (forward, backward, Adam, loss read
+        back) from step 10 on: the first steps also load torch's and Adam's
+        kernels.  grid: the handle the forward updates in place, or None for
+        a new grid per step."""
+        opt = torch.optim.Adam([theta], lr=args.lr_scale * h)
+        skip = min(10, steps // 2)
+        t0 = time.time()
+        for it in range(steps):
+            if it == skip:
+                torch.cuda.synchronize()
+                t0 = time.time()
+            opt.zero_grad()
+            loss = loss_of(theta, grid)
+            loss.backward()
+            opt.step()
+            losses.append(float(loss.detach()))
+            if it % 50 == 0:
+                log("adam step %d loss %.3e" % (it, losses[-1]))
+        torch.cuda.synchronize()
+        return (time.time() - t0) * 1e3 / max(steps - skip, 1), steps - skip
+
+    # a new grid per step, on a copy (for comparison only)
+    ms_new_grid, _ = run(theta0.clone().requires_grad_(True), 40, None, [])
     theta = theta0.clone().requires_grad_(True)
-    opt = torch.optim.Adam([theta], lr=args.lr_scale * h)
-    # wall clock per step (forward, backward, Adam, loss read back), timed from
-    # step 10 on: the first steps also load torch's and Adam's kernels
     losses = []
-    skip = min(10, args.adam_steps // 2)
-    t0 = time.time()
-    for it in range(args.adam_steps):
-        if it == skip:
-            torch.cuda.synchronize()
-            t0 = time.time()
-        opt.zero_grad()
-        loss = loss_of(theta)
-        loss.backward()
-        opt.step()
-        losses.append(float(loss.detach()))
-        if it % 50 == 0:
-            log("adam step %d loss %.3e" % (it, losses[-1]))
-    torch.cuda.synchronize()
-    step_ms = (time.time() - t0) * 1e3 / max(args.adam_steps - skip, 1)
+    step_ms, timed = run(theta, args.adam_steps, hyb.sdf_from_grid(theta0.clone(), g4), losses)
     after = artefact_rate(theta, Rh, target_h)
     # kernel times of one forward and one backward on the final grid
     sdf = hyb.sdf_from_grid(theta.detach().contiguous(), g4)
@@ -478,6 +486,12 @@ def bench_diff(args, torch, hyb, W, dev, stream):
         hyb.sdf_from_grid(x, g4)
     torch.cuda.synchronize()
     ms_upload = (time.time() - t1) * 1e3 / 20
+    torch.cuda.synchronize()
+    t1 = time.time()
+    for _ in range(20):
+        hyb.sdf_update(sdf, x)
+    torch.cuda.synchronize()
+    ms_update = (time.time() - t1) * 1e3 / 20
     log("refit: loss %.3e -> %.3e; artefacts %.4f -> %.4f; step %.2f ms" % (losses[0], losses[-1], before[0],
                                                                             after[0], step_ms))
     return {"config": "differentiation", "workload": "GI scene (%d triangles), 128^3 FP32 learnable grid, "
@@ -488,8 +502,9 @@ def bench_diff(args, torch, hyb, W, dev, stream):
             "loss_first": losses[0] if losses else None, "loss_last": losses[-1] if losses else None,
             "heldout_artefact_rate_before": before[0], "heldout_artefact_rate_after": after[0],
             "heldout_mean_dt_over_h_before": before[1], "heldout_mean_dt_over_h_after": after[1],
-            "ms_per_adam_step": step_ms, "adam_steps_timed": args.adam_steps - skip, "forward_kernel_ms": ms_fwd,
-            "backward_kernel_ms": ms_bwd, "sdf_from_grid_ms": ms_upload,
+            "ms_per_adam_step": step_ms, "adam_steps_timed": timed,
+            "ms_per_adam_step_new_grid_each_step": ms_new_grid, "forward_kernel_ms": ms_fwd,
+            "backward_kernel_ms": ms_bwd, "sdf_from_grid_ms": ms_upload, "sdf_update_ms": ms_update,
             "forward_mrays_s": rays.n / ms_fwd / 1e3, "backward_mrays_s": rays.n / ms_bwd / 1e3}
 
 

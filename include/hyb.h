@@ -167,6 +167,20 @@ hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t fl
 hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4, uint32_t flags,
                              hyb_sdf_format fmt, void* stream, hyb_sdf* out);
 
+/* Replace the samples of an existing grid in place (for loops that change a
+ * grid every step, such as refitting it by gradient descent): afterwards the
+ * handle holds what hyb_sdf_from_grid(values, n, grid4, flags, fmt) would
+ * give for its own n, grid4 and format, bounds included, in the device memory
+ * it already owns (nothing is allocated).
+ *   values  device, n^3 floats of the handle's n, x fastest
+ *   flags   0 or HYB_SDF_LIPSCHITZ_SAMPLES
+ * Synchronous on `stream` (the bounds are read back).  Work already queued on
+ * other streams that reads the handle must have finished.  Errors:
+ * HYB_ERR_INVALID_ARG for a NULL handle/values, unknown flags, a handle of
+ * another device, or non-finite values (the handle's samples are then
+ * undefined until the next successful update). */
+hyb_status hyb_sdf_update(hyb_sdf sdf, const float* values, uint32_t flags, void* stream);
+
 /* Grid placement, resolution and the Lipschitz bound L of the trilinear
  * interpolant of the stored samples (steps of g/L never pass a root; the
  * trace kernels step by g / min(L, L_d) with L_d = max(1, sum_i s_i |d_i|)

@@ -84,6 +84,7 @@ def lib() -> ctypes.CDLL:
             "hyb_bvh_info": [P, P, P, P],
             "hyb_build_sdf": [P, i32, P, u32, i32, P, PP],
             "hyb_sdf_from_grid": [P, i32, P, u32, i32, P, PP],
+            "hyb_sdf_update": [P, P, u32, P],
             "hyb_sdf_info": [P, P, P, P],
             "hyb_sdf_read": [P, P, P],
             "hyb_trace": [P, P, P, i64, f32, f32, P, P],
@@ -221,6 +222,22 @@ def sdf_from_grid(values, grid4, lipschitz_samples: bool = False, fmt: int = SDF
         _ptr(values), n, g.ctypes.data_as(ctypes.c_void_p), LIPSCHITZ_SAMPLES if lipschitz_samples else 0, fmt,
         _stream(stream), ctypes.byref(out)))
     return Sdf(out)
+
+
+def sdf_update(sdf: Sdf, values, lipschitz_samples: bool = False, stream=None) -> Sdf:
+    """Replace the samples of `sdf` in place by a CUDA float32 tensor of its
+    n^3 samples (x fastest), reusing its device memory; returns sdf."""
+    torch = _torch()
+    if not (values.is_cuda and values.dtype == torch.float32 and values.is_contiguous()):
+        raise ValueError("values must be a contiguous float32 CUDA tensor")
+    if values.numel() != sdf.n ** 3:
+        raise ValueError("values must hold the grid's n^3 samples")
+    _check("hyb_sdf_update", lib().hyb_sdf_update(sdf.handle, _ptr(values),
+                                                  LIPSCHITZ_SAMPLES if lipschitz_samples else 0, _stream(stream)))
+    L = ctypes.c_float()
+    _check("hyb_sdf_info", lib().hyb_sdf_info(sdf.handle, None, None, ctypes.byref(L)))
+    sdf.lipschitz = L.value
+    return sdf
 
 
 def sdf_read(sdf: Sdf, stream=None):

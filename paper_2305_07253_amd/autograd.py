@@ -7,19 +7,25 @@ differentiation of g(t; theta) = 0 at the hit, d t / d theta_j =
 -w_j / (grad f~ . d) for the 8 corners of the hit cell, with the hit point
 recomputed from the saved t rather than a stored ray path.  Lets a distance
 field be refit against triangle-hit targets to shrink its artefacts.
+
+With `sdf` given (a grid of theta's size and format), the forward writes theta
+into that handle with hyb_sdf_update instead of creating a grid per call; the
+backward then reads the handle, so it must run before the next forward that
+updates the same handle (the usual forward, backward, step loop).
 """
 from __future__ import annotations
 
 import torch
 
-from . import df_backward, sdf_from_grid, trace_df
+from . import df_backward, sdf_from_grid, sdf_update, trace_df
 
 
 class DFHit(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, theta, grid4, rays, tmax, tmin=None):
+    def forward(ctx, theta, grid4, rays, tmax, tmin=None, sdf=None):
         n = round(theta.numel() ** (1.0 / 3.0))
-        sdf = sdf_from_grid(theta.detach().contiguous().reshape(-1), grid4)
+        values = theta.detach().contiguous().reshape(-1)
+        sdf = sdf_from_grid(values, grid4) if sdf is None else sdf_update(sdf, values)
         t, prim, _, _ = trace_df(sdf, rays, tmax, tmin=tmin)
         ctx.sdf, ctx.tmax, ctx.n = sdf, float(tmax), n
         ctx.save_for_backward(rays, t, tmin if tmin is not None else torch.empty(0, device=t.device))
@@ -33,9 +39,9 @@ class DFHit(torch.autograd.Function):
         grad = torch.zeros(ctx.n ** 3, dtype=torch.float32, device=t.device)
         g = torch.nan_to_num(grad_t.contiguous().float(), nan=0.0, posinf=0.0, neginf=0.0)
         df_backward(ctx.sdf, rays, ctx.tmax, t, g, grad, tmin=tmin if ctx.has_tmin else None)
-        return grad.reshape(ctx.theta_shape), None, None, None, None
+        return grad.reshape(ctx.theta_shape), None, None, None, None, None
 
 
-def df_hit(theta, grid4, rays, tmax, tmin=None):
+def df_hit(theta, grid4, rays, tmax, tmin=None, sdf=None):
     """Differentiable DF hit distance of each ray (see module docstring)."""
-    return DFHit.apply(theta, grid4, rays, tmax, tmin)
+    return DFHit.apply(theta, grid4, rays, tmax, tmin, sdf)

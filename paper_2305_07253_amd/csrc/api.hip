@@ -171,6 +171,17 @@ hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4,
     return HYB_OK;
 }
 
+hyb_status hyb_sdf_update(hyb_sdf sdf, const float* values, uint32_t flags, void* stream) {
+    if (!sdf || !values || (flags & ~HYB_SDF_LIPSCHITZ_SAMPLES) || !same_device(sdf->device))
+        return HYB_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t bytes = sizeof(float) * static_cast<size_t>(sdf->n) * sdf->n * sdf->n;
+    sdf->certified = (flags & HYB_SDF_LIPSCHITZ_SAMPLES) != 0;
+    HYB_TRY(hipMemcpyAsync(sdf->values, values, bytes, hipMemcpyDeviceToDevice, st));
+    HYB_TRY(hyb::launch_quantize(sdf->layout, sdf->values, sdf->n, sdf->store, sdf->scales, st));
+    return compute_lipschitz(sdf, st);
+}
+
 hyb_status hyb_sdf_info(hyb_sdf sdf, float* grid4, int32_t* n, float* lipschitz) {
     if (!sdf) return HYB_ERR_INVALID_ARG;
     if (grid4) std::memcpy(grid4, sdf->grid4, sizeof(sdf->grid4));
@@ -190,6 +201,7 @@ hyb_status hyb_sdf_destroy(hyb_sdf sdf) {
     if (sdf->values) (void)hipFree(sdf->values);
     if (sdf->store) (void)hipFree(sdf->store);
     if (sdf->scales) (void)hipFree(sdf->scales);
+    if (sdf->blocks) (void)hipFree(sdf->blocks);
     delete sdf;
     return HYB_OK;
 }

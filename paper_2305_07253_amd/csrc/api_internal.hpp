@@ -38,6 +38,7 @@ struct hyb_sdf_s {
     bool certified = false;  // samples are FP32 roundings of a 1-Lipschitz function
     hyb_sdf_format fmt = HYB_SDF_F32;
     int32_t layout = 0;  // the kernels' storage format and brick layout (hyb::SdfFormat)
+    float* blocks = nullptr;  // per-block maxima of the bound pass (kept for updates)
 };
 
 namespace hyb_api {
@@ -69,15 +70,14 @@ inline bool valid_hits(const hyb_hits* h) { return h && h->t && h->prim && h->u 
 // maxima on the device, final maxima on the host (build time; synchronous).
 inline hyb_status compute_lipschitz(hyb_sdf_s* s, hipStream_t stream) {
     const int32_t nb = hyb::lipschitz_blocks(s->n);
-    float* d_blocks = nullptr;
-    HYB_TRY(hipMalloc(&d_blocks, sizeof(float) * 4 * nb));
+    if (!s->blocks) HYB_TRY(hipMalloc(&s->blocks, sizeof(float) * 4 * nb));
+    float* d_blocks = s->blocks;
     int32_t got = 0;
     hipError_t e = hyb::launch_lipschitz(s->values, s->n, s->grid4[3], d_blocks, &got, stream);
     std::vector<float> host(4 * static_cast<size_t>(nb), 0.0f);
     if (e == hipSuccess)
         e = hipMemcpyAsync(host.data(), d_blocks, sizeof(float) * 4 * nb, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    (void)hipFree(d_blocks);
     HYB_TRY(e);
     float m[4] = {0, 0, 0, 0};
     for (size_t b = 0; b < static_cast<size_t>(nb); ++b)

@@ -1,0 +1,110 @@
+"""GPU: hyb_sdf_update (samples replaced in place) leaves a handle equal to a
+fresh hyb_sdf_from_grid of the same samples: bounds, stored samples and every
+trace result bit for bit, in each format; and the refit's autograd path gives
+the same hits, and gradients up to the order of float atomics, with an
+updated handle as with a grid per call."""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TMAX = 2.0
+
+
+@pytest.fixture(scope="module")
+def hyb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2305_07253_amd as hyb
+    hyb.lib()
+    return hyb
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.fixture(scope="module")
+def grids(tiny):
+    """The tiny room's exact grid and a perturbed copy (a refit step's kind of
+    change: small, every node)."""
+    g1 = tiny["grid"].astype(np.float32)
+    rng = np.random.default_rng(31)
+    g2 = (g1 + 0.02 * tiny["grid4"][3] * rng.standard_normal(g1.shape)).astype(np.float32)
+    return g1, g2
+
+
+def _all_outputs(hyb, bvh, sdf, R):
+    out = []
+    for tau in (0.0, 1.0):
+        out += [x.cpu().numpy() for x in hyb.trace(bvh, sdf, R, TMAX, tau)]
+    out += [x.cpu().numpy() for x in hyb.trace_df(sdf, R, TMAX)]
+    return out
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("certified", [False, True])
+def test_update_equals_fresh_grid(hyb, tiny, grids, fmt, certified):
+    g1, g2 = grids
+    sc = tiny["scene"]
+    bvh = hyb.build_bvh(sc.verts, sc.tris)
+    R = _dev(tiny["free"].soa())
+    a = hyb.sdf_from_grid(_dev(g1.reshape(-1)), tiny["grid4"], fmt=fmt)
+    first = _all_outputs(hyb, bvh, a, R)
+    for g in (g2, g1, g2):  # repeated updates, each against its own fresh grid
+        hyb.sdf_update(a, _dev(g.reshape(-1)), lipschitz_samples=certified)
+        b = hyb.sdf_from_grid(_dev(g.reshape(-1)), tiny["grid4"], lipschitz_samples=certified, fmt=fmt)
+        assert a.lipschitz == b.lipschitz
+        assert np.array_equal(hyb.sdf_read(a).cpu().numpy(), hyb.sdf_read(b).cpu().numpy())
+        for k, (x, y) in enumerate(zip(_all_outputs(hyb, bvh, a, R), _all_outputs(hyb, bvh, b, R))):
+            assert np.array_equal(x, y), (fmt, certified, k)
+    # the perturbation changes results, so the comparison above is not vacuous
+    assert not all(np.array_equal(x, y) for x, y in zip(first, _all_outputs(hyb, bvh, a, R)))
+
+
+def test_update_rejects_bad_input(hyb, tiny, grids):
+    g1, _ = grids
+    a = hyb.sdf_from_grid(_dev(g1.reshape(-1)), tiny["grid4"])
+    L = hyb.lib()
+    assert L.hyb_sdf_update(None, hyb._ptr(_dev(g1.reshape(-1))), 0, None) == 1
+    assert L.hyb_sdf_update(a.handle, None, 0, None) == 1
+    assert L.hyb_sdf_update(a.handle, hyb._ptr(_dev(g1.reshape(-1))), ctypes.c_uint32(0x80), None) == 1
+    bad = g1.copy()
+    bad[3, 4, 5] = np.inf
+    assert L.hyb_sdf_update(a.handle, hyb._ptr(_dev(bad.reshape(-1))), 0, None) == 1
+    with pytest.raises(ValueError):
+        hyb.sdf_update(a, _dev(g1.reshape(-1)[:-1]))
+    # a later valid update restores the handle
+    hyb.sdf_update(a, _dev(g1.reshape(-1)))
+    b = hyb.sdf_from_grid(_dev(g1.reshape(-1)), tiny["grid4"])
+    R = _dev(tiny["surf"].soa())
+    assert a.lipschitz == b.lipschitz
+    for x, y in zip(hyb.trace_df(a, R, TMAX), hyb.trace_df(b, R, TMAX)):
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+
+
+def test_autograd_with_updated_handle(hyb, tiny, grids):
+    import torch
+    from paper_2305_07253_amd.autograd import df_hit
+    g1, g2 = grids
+    R = _dev(tiny["surf"].soa())
+    handle = hyb.sdf_from_grid(_dev(g1.reshape(-1)), tiny["grid4"])
+    for g in (g2, g1):
+        res = []
+        for grid in (None, handle):
+            theta = _dev(g.reshape(-1)).requires_grad_(True)
+            t = df_hit(theta, tiny["grid4"], R, TMAX, sdf=grid)
+            w = torch.where(torch.isfinite(t), t, torch.zeros_like(t))
+            (w * w).sum().backward()
+            torch.cuda.synchronize()
+            res.append((t.detach().cpu().numpy(), theta.grad.cpu().numpy()))
+        assert np.array_equal(res[0][0], res[1][0])
+        # the backward adds into the gradient with float atomics, whose order
+        # varies between launches
+        scale = np.abs(res[0][1]).max()
+        assert scale > 0
+        np.testing.assert_allclose(res[0][1], res[1][1], rtol=1e-5, atol=1e-6 * scale)
