@@ -215,7 +215,11 @@ hyb_status hyb_trace(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, 
     hyb::TraceArgs a;
     fill_trace_args(a, rays, hits, n, tmax, threshold);
     fill_scene(a, bvh, sdf);
-    return from_hip(hyb::launch_trace(hyb::kCombined, false, a, static_cast<hipStream_t>(stream)));
+    // Threshold 0 leaves the triangle segment empty (t1 = tmin), so the query
+    // is the distance-field query on [tmin, tmax]: its own kernel runs it, the
+    // same per-ray arithmetic without the traversal code or the LDS stack.
+    const int mode = threshold == 0.0f ? hyb::kDfOnly : hyb::kCombined;
+    return from_hip(hyb::launch_trace(mode, false, a, static_cast<hipStream_t>(stream)));
 }
 
 hyb_status hyb_trace_bvh(hyb_bvh bvh, const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits, void* stream) {
