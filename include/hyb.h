@@ -27,8 +27,8 @@
  *    the first launch after a change of launch shape).
  *  - Errors come back as a status, never as a crash or an exception.  A status
  *    other than HYB_OK leaves outputs unspecified.
- *  - BVH and distance-field handles are immutable after build: concurrent trace
- *    calls on different streams are safe.  A batch handle is mutable (its
+ *  - BVH and distance-field handles are immutable after build (except through
+ *    hyb_sdf_update): concurrent trace calls on different streams are safe.  A batch handle is mutable (its
  *    thresholds and launch shape): calls on one batch must be ordered.
  */
 #ifndef HYB_H
@@ -154,16 +154,22 @@ hyb_status hyb_bvh_info(hyb_bvh bvh, int64_t* n_nodes, int64_t* n_tris, int32_t*
 hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t flags, hyb_sdf_format fmt,
                          void* stream, hyb_sdf* out);
 
-/* Wrap caller-provided samples as a distance field (copied).
+/* Wrap caller-provided samples as the distance field the DF sub-queries trace
+ * (Section 3, "Distance Field Generation": the paper builds its field from the
+ * scene every frame or incrementally; this takes a field built elsewhere, e.g.
+ * analytic test fields or a field refit by gradient descent).  Copied.
  *   values  device, n^3 floats, x fastest: values[i + n (j + n k)]; 2 <= n <= 1024
  *   grid4   host, {lo_x, lo_y, lo_z, h}
  *   flags   0 or HYB_SDF_LIPSCHITZ_SAMPLES
  *   fmt     storage format the values are converted to
  * The bounds used for safe steps (the Lipschitz bound and per-axis bounds of
  * the partial derivatives) are recomputed from the stored (dequantized)
- * values.
+ * values.  Any finite samples are traced exactly (the first root of their
+ * interpolant), however large their bound: a march whose steps would be short
+ * walks cell by cell instead.
  * Errors: HYB_ERR_INVALID_ARG for NULL values/grid4/out, bad n, h <= 0,
- * non-finite grid4 or unknown flags. */
+ * non-finite grid4, unknown flags, or a sample that is NaN or infinite (or,
+ * for HYB_SDF_F16, beyond the half range). */
 hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4, uint32_t flags,
                              hyb_sdf_format fmt, void* stream, hyb_sdf* out);
 
@@ -175,20 +181,30 @@ hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4,
  *   values  device, n^3 floats of the handle's n, x fastest
  *   flags   0 or HYB_SDF_LIPSCHITZ_SAMPLES
  * Synchronous on `stream` (the bounds are read back).  Work already queued on
- * other streams that reads the handle must have finished.  Errors:
- * HYB_ERR_INVALID_ARG for a NULL handle/values, unknown flags, a handle of
- * another device, or non-finite values (the handle's samples are then
- * undefined until the next successful update). */
+ * other streams that reads the handle must have finished.  Batches that hold
+ * the handle use the new samples and bounds from their next launch on.
+ * Errors: HYB_ERR_INVALID_ARG for a NULL handle/values, unknown flags, a
+ * handle of another device, or a sample that is NaN or infinite (or, for
+ * HYB_SDF_F16, beyond the half range); the handle's samples are then undefined
+ * until the next successful update. */
 hyb_status hyb_sdf_update(hyb_sdf sdf, const float* values, uint32_t flags, void* stream);
 
+/* Voxel size h of the grid: the unit of the switch thresholds (Section 3,
+ * "Occlusion Queries": t1 is computed from the voxel size times a user
+ * multiplier; "GI & Shadow Rays": t1 and t2 likewise).  Errors:
+ * HYB_ERR_INVALID_ARG for a NULL sdf or h. */
+hyb_status hyb_sdf_voxel_size(hyb_sdf sdf, float* h);
+
 /* Grid placement, resolution and the Lipschitz bound L of the trilinear
- * interpolant of the stored samples (steps of g/L never pass a root; the
- * trace kernels step by g / min(L, L_d) with L_d = max(1, sum_i s_i |d_i|)
- * from per-axis slope bounds s_i, the ray's own bound). */
+ * interpolant of the stored samples (the distance field of Section 3,
+ * "Distance Field Generation"; steps of g/L never pass a root; the trace
+ * kernels step by g / min(L, L_d) with L_d = max(1, sum_i s_i |d_i|) from
+ * per-axis slope bounds s_i, the ray's own bound).  Each output may be NULL. */
 hyb_status hyb_sdf_info(hyb_sdf sdf, float* grid4 /* host, 4 */, int32_t* n, float* lipschitz);
 
-/* Copy the samples as the trace kernels see them (dequantized for compact
- * formats) into out (device, n^3 floats, x fastest). */
+/* Copy the samples of the distance field (Section 3, "Distance Field
+ * Generation") as the trace kernels see them (dequantized for compact
+ * formats) into out (device, n^3 floats, x fastest); asynchronous on stream. */
 hyb_status hyb_sdf_read(hyb_sdf sdf, float* out, void* stream);
 
 /* The combined first-hit query (Section 2, Eq. 2; Section 3): triangles on
@@ -197,14 +213,23 @@ hyb_status hyb_sdf_read(hyb_sdf sdf, float* out, void* stream);
  *   tmax       0 <= tmax, may be +inf
  *   threshold  0 <= threshold, in voxels of the grid, may be +inf
  * n == 0 is a no-op.  Errors: HYB_ERR_INVALID_ARG for NULL handles/pointers,
- * n < 0 or n > HYB_MAX_RAYS, NaN or negative tmax/threshold. */
+ * n < 0 or n > HYB_MAX_RAYS, NaN or negative tmax/threshold.
+ * The distance-field march is bounded by the cells the segment crosses and
+ * ends with the exact first root on any grid; a ray whose march ran out of
+ * iterations would be reported as prim -2 with t = NaN, never as a miss (the
+ * bound makes this unreachable). */
 hyb_status hyb_trace(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, float threshold,
                      hyb_hits* hits, void* stream);
 
-/* Pure triangle tracing on [tmin, tmax] (the paper's HWRT-only baseline). */
+/* Pure triangle tracing on [tmin, tmax]: the "HWRT only" technique the paper
+ * compares against (Section 3, the pure techniques "where all overhead is
+ * circumvented"; the first columns of Fig. 1 and Fig. 2).  Same outputs and
+ * errors as hyb_trace, with no distance field. */
 hyb_status hyb_trace_bvh(hyb_bvh bvh, const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits, void* stream);
 
-/* Pure distance-field tracing on [tmin, tmax] (the paper's DF-only baseline). */
+/* Pure distance-field tracing on [tmin, tmax]: the "DF only" technique of
+ * Section 3 (the last columns of Fig. 1 and Fig. 2).  Every hit has prim -2.
+ * Same errors as hyb_trace, with no BVH. */
 hyb_status hyb_trace_df(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, hyb_hits* hits, void* stream);
 
 /* The paper's shadow-ray query (Section 3, GI & shadow rays; Section 2,
@@ -267,7 +292,8 @@ hyb_status hyb_sdf_destroy(hyb_sdf sdf);
  *
  * The batch keeps the item's pointers: the bvh, sdf, ray and hit buffers must
  * stay valid until hyb_batch_destroy; new ray data may be written into the same
- * buffers between launches.  All calls on one batch must be ordered (one
+ * buffers between launches, and an sdf replaced in place by hyb_sdf_update is
+ * read again (samples, bounds) at the next launch or tune.  All calls on one batch must be ordered (one
  * stream, or synchronised by the caller): the batch's counter and descriptor
  * table are shared by its launches.
  * ------------------------------------------------------------------------ */

@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
             "hyb_sdf_from_grid": [P, i32, P, u32, i32, P, PP],
             "hyb_sdf_update": [P, P, u32, P],
             "hyb_sdf_info": [P, P, P, P],
+            "hyb_sdf_voxel_size": [P, P],
             "hyb_sdf_read": [P, P, P],
             "hyb_trace": [P, P, P, i64, f32, f32, P, P],
             "hyb_trace_bvh": [P, P, i64, f32, P, P],
@@ -173,7 +174,10 @@ class Sdf:
 
     @property
     def h(self) -> float:
-        return float(self.grid4[3])
+        """Voxel size (hyb_sdf_voxel_size): the unit of the switch thresholds."""
+        h = ctypes.c_float()
+        _check("hyb_sdf_voxel_size", lib().hyb_sdf_voxel_size(self._h, ctypes.byref(h)))
+        return h.value
 
     @property
     def handle(self):

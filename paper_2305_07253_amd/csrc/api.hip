@@ -161,6 +161,8 @@ hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4,
     if (e == hipSuccess) e = hipMalloc(&s->values, bytes);
     if (e == hipSuccess) e = hipMemcpyAsync(s->values, values, bytes, hipMemcpyDeviceToDevice, st);
     hyb_status rc = from_hip(e);
+    // the compact formats would turn a NaN input into a finite code
+    if (rc == HYB_OK && fmt != HYB_SDF_F32) rc = check_finite(s, st);
     if (rc == HYB_OK) rc = quantize(s, st);
     if (rc == HYB_OK) rc = compute_lipschitz(s, st);
     if (rc != HYB_OK) {
@@ -178,8 +180,19 @@ hyb_status hyb_sdf_update(hyb_sdf sdf, const float* values, uint32_t flags, void
     const size_t bytes = sizeof(float) * static_cast<size_t>(sdf->n) * sdf->n * sdf->n;
     sdf->certified = (flags & HYB_SDF_LIPSCHITZ_SAMPLES) != 0;
     HYB_TRY(hipMemcpyAsync(sdf->values, values, bytes, hipMemcpyDeviceToDevice, st));
+    if (sdf->fmt != HYB_SDF_F32) {
+        // the compact formats would turn a NaN input into a finite code
+        const hyb_status rc = check_finite(sdf, st);
+        if (rc != HYB_OK) return rc;
+    }
     HYB_TRY(hyb::launch_quantize(sdf->layout, sdf->values, sdf->n, sdf->store, sdf->scales, st));
     return compute_lipschitz(sdf, st);
+}
+
+hyb_status hyb_sdf_voxel_size(hyb_sdf sdf, float* h) {
+    if (!sdf || !h) return HYB_ERR_INVALID_ARG;
+    *h = sdf->grid4[3];
+    return HYB_OK;
 }
 
 hyb_status hyb_sdf_info(hyb_sdf sdf, float* grid4, int32_t* n, float* lipschitz) {

@@ -39,6 +39,7 @@ struct hyb_sdf_s {
     hyb_sdf_format fmt = HYB_SDF_F32;
     int32_t layout = 0;  // the kernels' storage format and brick layout (hyb::SdfFormat)
     float* blocks = nullptr;  // per-block maxima of the bound pass (kept for updates)
+    uint64_t version = 0;     // bumped whenever the samples and bounds change (batches re-read them)
 };
 
 namespace hyb_api {
@@ -66,26 +67,46 @@ inline bool valid_rays(const hyb_rays* r) {
 
 inline bool valid_hits(const hyb_hits* h) { return h && h->t && h->prim && h->u && h->v; }
 
-// Lipschitz bound and per-axis slope bounds of the stored grid: per-block
-// maxima on the device, final maxima on the host (build time; synchronous).
-inline hyb_status compute_lipschitz(hyb_sdf_s* s, hipStream_t stream) {
+// The bound pass over s->values (n^3, x fastest) into host maxima m[0..4]
+// (see launch_lipschitz); synchronous.
+inline hyb_status grid_bounds(hyb_sdf_s* s, hipStream_t stream, float m[hyb::kBoundValues]) {
+    constexpr int V = hyb::kBoundValues;
     const int32_t nb = hyb::lipschitz_blocks(s->n);
-    if (!s->blocks) HYB_TRY(hipMalloc(&s->blocks, sizeof(float) * 4 * nb));
-    float* d_blocks = s->blocks;
+    if (!s->blocks) HYB_TRY(hipMalloc(&s->blocks, sizeof(float) * V * nb));
     int32_t got = 0;
-    hipError_t e = hyb::launch_lipschitz(s->values, s->n, s->grid4[3], d_blocks, &got, stream);
-    std::vector<float> host(4 * static_cast<size_t>(nb), 0.0f);
+    hipError_t e = hyb::launch_lipschitz(s->values, s->n, s->grid4[3], s->blocks, &got, stream);
+    std::vector<float> host(V * static_cast<size_t>(nb), 0.0f);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(host.data(), d_blocks, sizeof(float) * 4 * nb, hipMemcpyDeviceToHost, stream);
+        e = hipMemcpyAsync(host.data(), s->blocks, sizeof(float) * V * nb, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     HYB_TRY(e);
-    float m[4] = {0, 0, 0, 0};
+    for (int c = 0; c < V; ++c) m[c] = 0.0f;
     for (size_t b = 0; b < static_cast<size_t>(nb); ++b)
-        for (int c = 0; c < 4; ++c) m[c] = std::max(m[c], host[4 * b + c]);
+        for (int c = 0; c < V; ++c) m[c] = std::max(m[c], host[V * b + c]);
+    return HYB_OK;
+}
+
+// HYB_ERR_INVALID_ARG when some sample in s->values is NaN or infinite.
+inline hyb_status check_finite(hyb_sdf_s* s, hipStream_t stream) {
+    float m[hyb::kBoundValues];
+    const hyb_status rc = grid_bounds(s, stream, m);
+    if (rc != HYB_OK) return rc;
+    return m[4] != 0.0f ? HYB_ERR_INVALID_ARG : HYB_OK;
+}
+
+// Lipschitz bound and per-axis slope bounds of the stored grid: per-block
+// maxima on the device, final maxima on the host (build time; synchronous).
+// A stored sample that is not finite (e.g. an F16 overflow) is an error.
+inline hyb_status compute_lipschitz(hyb_sdf_s* s, hipStream_t stream) {
+    float m[hyb::kBoundValues];
+    const hyb_status rc = grid_bounds(s, stream, m);
+    if (rc != HYB_OK) return rc;
     for (float v : m)
         if (!std::isfinite(v)) return HYB_ERR_INVALID_ARG;
+    if (m[4] != 0.0f) return HYB_ERR_INVALID_ARG;
     s->lipschitz = hyb::finish_lipschitz(m[0]);
     for (int c = 0; c < 3; ++c) s->slope[c] = hyb::finish_slope(m[1 + c]);
+    ++s->version;
     return HYB_OK;
 }
 

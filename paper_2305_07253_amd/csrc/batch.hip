@@ -149,6 +149,8 @@ struct hyb_batch_s {
     int n_cu = 0;
     std::vector<hyb::TraceArgs> args;  // per item; tau is the item's current threshold
     std::vector<uint8_t> kind;
+    std::vector<const hyb_sdf_s*> sdfs;  // per item (null: triangles only)
+    std::vector<uint64_t> sdf_version;   // each sdf's version when its fields were copied into args
     std::vector<uint32_t> item_start;  // host copy for the current rays_per_item
     hyb::TraceArgs* d_args = nullptr;
     uint32_t* d_item_start = nullptr;
@@ -177,9 +179,23 @@ void drop_graph(hyb_batch_s* b) {
     b->graph_dirty = true;
 }
 
+// A grid replaced in place (hyb_sdf_update) has new step bounds and possibly
+// a new certification: copy its fields into the item's arguments again.
+void refresh_grids(hyb_batch_s* b) {
+    for (size_t i = 0; i < b->sdfs.size(); ++i) {
+        const hyb_sdf_s* sdf = b->sdfs[i];
+        if (sdf && sdf->version != b->sdf_version[i]) {
+            fill_scene(b->args[i], nullptr, sdf);
+            b->sdf_version[i] = sdf->version;
+            b->table_dirty = true;
+        }
+    }
+}
+
 // Uploads the descriptor table and the item offsets for the current config and
 // fixes the launch grid (synchronous on `stream`).
 hyb_status sync_table(hyb_batch_s* b, hipStream_t stream) {
+    refresh_grids(b);
     if (!b->table_dirty) return HYB_OK;
     const int32_t n_scenes = static_cast<int32_t>(b->args.size());
     uint64_t total = 0;
@@ -353,6 +369,8 @@ hyb_status hyb_batch_create(const hyb_batch_item* items, int32_t n_items, void* 
     b->fmt = fmt < 0 ? hyb::kF32 : fmt;
     b->args.resize(n_items);
     b->kind.resize(n_items);
+    b->sdfs.resize(n_items);
+    b->sdf_version.resize(n_items);
     b->item_start.resize(n_items + 1);
     for (int32_t i = 0; i < n_items; ++i) {
         const hyb_batch_item& it = items[i];
@@ -361,6 +379,8 @@ hyb_status hyb_batch_create(const hyb_batch_item* items, int32_t n_items, void* 
         fill_scene(a, it.bvh, it.sdf);
         if (!it.sdf) a.h = 1.0f;  // t1 = fma(+inf, h, tmin) must be +inf (then min(., tmax) = tmax), not NaN
         b->kind[i] = !it.sdf ? kTrianglesOnly : (!it.bvh ? kFieldOnly : kBoth);
+        b->sdfs[i] = it.sdf;
+        b->sdf_version[i] = it.sdf ? it.sdf->version : 0;
     }
     hipError_t e = hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipMalloc(&b->d_args, sizeof(hyb::TraceArgs) * n_items);
@@ -447,6 +467,7 @@ hyb_status hyb_batch_tune(hyb_batch batch, const hyb_batch_tune_opts* opts, floa
         if (std::isnan(c) || c < 0.0f) return HYB_ERR_INVALID_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int32_t n_items = static_cast<int32_t>(batch->args.size());
+    refresh_grids(batch);
     if (item_error)
         for (int32_t i = 0; i < n_items; ++i) item_error[i] = 0.0f;
 

@@ -520,6 +520,7 @@ struct DfRay {
     int ci, cj, ck;     // current cell while walking
     bool walk;
     bool relax;         // the next sphere step may be over-relaxed
+    bool walk_only;     // cell steps only (the bounded fall-back of df_first_root)
     // a cell span [t, t + span] whose cubic k may vanish, left for df_resolve
     float k[4], span, t_exit;
     int axis;           // exit face of that cell: 0, 1, 2
@@ -585,6 +586,7 @@ HYB_HD bool df_init(const Grid& g, float ox, float oy, float oz, float dx, float
     r.ci = r.cj = r.ck = 0;
     r.walk = false;
     r.relax = false;
+    r.walk_only = false;
     return true;
 }
 
@@ -632,7 +634,12 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
         return kDfContinue;
     }
     if (val <= 0.0f) return kDfHit;
-    if (val > g.h) {
+    // A sphere step far from the surface, unless it would be shorter than half
+    // a cell: on a grid whose bound L is inflated (one extreme sample anywhere
+    // makes every step short) the exact cell step is longer.  For any grid
+    // with L < 2, g > h already gives safe > h / 2, so this only changes
+    // the march on such grids.
+    if (val > g.h && safe >= 0.5f * g.h && !r.walk_only) {
         r.walk = false;
         r.cover = r.t + safe;
         r.t += r.relax ? kOverRelax * safe : safe;
@@ -674,11 +681,22 @@ HYB_HD int df_resolve(const Grid& g, DfRay& r) {
     return df_advance(g, r, r.axis, r.t_exit);
 }
 
-// Upper bound on the iterations of one march: sphere steps are at least
-// h / L >= h / sqrt(3) long (an over-relaxed step the next iteration takes
-// back is followed by a plain one), cell steps enter a new cell along the ray,
-// and the clipped segment is at most sqrt(3) (n - 1) h long.
-HYB_HD int df_max_steps(const Grid& g) { return 16 * g.n + 64; }
+// Iterations of the mixed march before the walk-only fall-back: sphere steps
+// are at least h / 2 long (an over-relaxed step the next iteration takes
+// back is followed by a plain one), cell steps enter a new cell along the
+// ray, and the clipped segment is at most sqrt(3) (n - 1) h long, so this is
+// not reached in practice; it only has to keep the march finite.  (A host
+// build of these functions may define a smaller budget to exercise the
+// fall-back.)
+#ifndef HYB_DF_MIXED_STEPS
+#define HYB_DF_MIXED_STEPS(n) (16 * (n) + 64)
+#endif
+HYB_HD int df_max_steps(const Grid& g) { return HYB_DF_MIXED_STEPS(g.n); }
+
+// Iterations of the walk-only fall-back: every iteration either ends the
+// march or moves one of the three cell indices one step in the direction of
+// the ray, and each index stays in [0, n - 2].
+HYB_HD int df_max_walk(const Grid& g) { return 3 * g.n; }
 
 // First t in [a, b] (clipped to the grid box) where the trilinear interpolant
 // of the samples is <= 0, or +inf.
@@ -713,7 +731,19 @@ HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx
         for (; budget > 0 && st == kDfContinue; --budget) st = df_step<FMT, COUNT>(g, r, cnt);
         if (st == kDfSolve) st = df_resolve(g, r);
         if (st == kDfHit) return r.t;
-        if (st == kDfMiss || budget <= 0) return __builtin_inff();
+        if (st == kDfMiss) return __builtin_inff();
+        if (budget <= 0) {
+            // Out of iterations without an answer: walk cell by cell from the
+            // end of the part of the ray already verified free of roots.  The
+            // walk visits each crossed cell once and is exact, so the result
+            // is still the first root.  A walk that ran out too (impossible
+            // by the bound above) reports NaN, never a miss.
+            if (r.walk_only) return __builtin_nanf("");
+            r.t = r.cover;
+            r.walk = false;
+            r.walk_only = true;
+            budget = df_max_walk(g);
+        }
     }
 }
 
@@ -850,7 +880,7 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
                                                  entry_node(a, ox, oy, oz, dx, dy, dz, tmin, tmax));
         } else if (MODE == kDfOnly) {
             const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, tmin, tmax, cnt);
-            if (t < __builtin_inff()) {
+            if (t != __builtin_inff()) {  // NaN: see df_first_root
                 hit.t = t;
                 hit.prim = -2;
             }
@@ -862,7 +892,7 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
             const float t2 = fmaxf(fmaf(-a.tau_end, a.h, tmax), t1);
             if (t2 > t1 || (a.tau == 0.0f && a.tau_end == 0.0f)) {
                 const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, t2, cnt);
-                if (t < __builtin_inff()) {
+                if (t != __builtin_inff()) {  // NaN: see df_first_root
                     hit.t = t;
                     hit.prim = -2;
                 }
@@ -883,7 +913,7 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
                                                      cnt, entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1));
             if (hit.prim < 0 && (t1 < tmax || a.tau == 0.0f)) {
                 const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, tmax, cnt);
-                if (t < __builtin_inff()) {
+                if (t != __builtin_inff()) {  // NaN: see df_first_root
                     hit.t = t;
                     hit.prim = -2;
                 }

@@ -90,8 +90,11 @@ struct SdfBuildArgs {
 hipError_t launch_sdf_build(const SdfBuildArgs& a, hipStream_t stream);
 
 // Per-block maxima of the cell Lipschitz bounds and of the per-axis cell
-// slopes of an n^3 grid (x fastest): block b writes block_max[4 b .. 4 b + 4)
-// = (Lipschitz, slope x, slope y, slope z); returns n_blocks through *n_blocks.
+// slopes of an n^3 grid (x fastest), and a flag for non-finite samples: block
+// b writes block_max[5 b .. 5 b + 5) = (Lipschitz, slope x, slope y, slope z,
+// 1 if some sample of its cells is NaN or infinite else 0); returns n_blocks
+// through *n_blocks.
+constexpr int kBoundValues = 5;
 hipError_t launch_lipschitz(const float* grid, int32_t n, float h, float* block_max, int32_t* n_blocks,
                             hipStream_t stream);
 int32_t lipschitz_blocks(int32_t n);

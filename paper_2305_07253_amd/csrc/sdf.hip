@@ -19,12 +19,14 @@ __global__ __launch_bounds__(256) void k_sdf_build(SdfBuildArgs a) {
 }
 
 // Largest cell gradient bound of the grid (cell_lipschitz) and largest
-// per-axis slopes (cell_slopes): 4 values per block.
+// per-axis slopes (cell_slopes), and whether any sample is not finite (fmaxf
+// drops NaN, so that is tested on its own): kBoundValues values per block.
 __global__ __launch_bounds__(256) void k_lipschitz(const float* __restrict__ g, int32_t n, float inv_h,
                                                    float* __restrict__ block_max) {
-    __shared__ float red[4][256];
+    constexpr int V = kBoundValues;
+    __shared__ float red[V][256];
     const int64_t m = n - 1;
-    float best[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float best[V] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < m * m * m; c += (int64_t)gridDim.x * 256) {
         const int64_t i = c % m, j = (c / m) % m, k = c / (m * m);
         const float* p = g + i + (int64_t)n * (j + (int64_t)n * k);
@@ -34,15 +36,17 @@ __global__ __launch_bounds__(256) void k_lipschitz(const float* __restrict__ g, 
         cell_slopes(f, inv_h, s);
         best[0] = fmaxf(best[0], cell_lipschitz(f, inv_h));
         for (int a = 0; a < 3; ++a) best[1 + a] = fmaxf(best[1 + a], s[a]);
+        for (int q = 0; q < 8; ++q)
+            if (!(fabsf(f[q]) <= 3.402823466e38f)) best[4] = 1.0f;  // NaN or +-inf
     }
-    for (int a = 0; a < 4; ++a) red[a][threadIdx.x] = best[a];
+    for (int a = 0; a < V; ++a) red[a][threadIdx.x] = best[a];
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if (threadIdx.x < s)
-            for (int a = 0; a < 4; ++a) red[a][threadIdx.x] = fmaxf(red[a][threadIdx.x], red[a][threadIdx.x + s]);
+            for (int a = 0; a < V; ++a) red[a][threadIdx.x] = fmaxf(red[a][threadIdx.x], red[a][threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x < 4) block_max[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < V) block_max[V * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // I8 block scales: one thread per 8^3 block of nodes, max |f| / 127.

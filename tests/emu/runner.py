@@ -16,28 +16,33 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2305_07253_amd", "csrc")
 BUILD = os.path.join(HERE, "_build")
 EXE = os.path.join(BUILD, "emu")
+# The same bodies with a distance-field march budget of 4 mixed iterations, so
+# that nearly every ray finishes in the walk-only fall-back.
+EXE_WALK = os.path.join(BUILD, "emu_walk")
 
 
-def build(force: bool = False) -> str:
+def build(force: bool = False, walk: bool = False) -> str:
+    exe = EXE_WALK if walk else EXE
     srcs = [os.path.join(HERE, "emu.cpp"), os.path.join(CSRC, "bvh_build.cpp")]
     deps = srcs + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
-    if not force and os.path.exists(EXE) and os.path.getmtime(EXE) >= max(os.path.getmtime(d) for d in deps):
-        return EXE
+    if not force and os.path.exists(exe) and os.path.getmtime(exe) >= max(os.path.getmtime(d) for d in deps):
+        return exe
     os.makedirs(BUILD, exist_ok=True)
-    tmp = EXE + ".tmp%d" % os.getpid()
+    tmp = exe + ".tmp%d" % os.getpid()
     cmd = ["/opt/rocm/bin/hipcc", "-x", "hip", "--offload-host-only", "-O1", "-g", "-std=c++17",
            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
            "-Xarch_host", "-fno-sanitize-recover=undefined",
+           *(["-DHYB_DF_MIXED_STEPS(n)=4"] if walk else []),
            "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError(r.stdout)
-    os.replace(tmp, EXE)
-    return EXE
+    os.replace(tmp, exe)
+    return exe
 
 
-def _run(hdr, par, arrays, out_bytes):
-    exe = build()
+def _run(hdr, par, arrays, out_bytes, walk=False):
+    exe = build(walk=walk)
     with tempfile.TemporaryDirectory() as d:
         fin, fout = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
         with open(fin, "wb") as f:
@@ -55,12 +60,13 @@ def _run(hdr, par, arrays, out_bytes):
 
 
 def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, certified=False, fmt=0, tmax_ray=None,
-          tau_end=0.0):
+          tau_end=0.0, walk=False):
     """Returns (t, prim, u, v, counts) exactly as the kernels compute them;
     `certified` marks the grid samples as exact distances; `fmt` stores the
     FP32 grid as F16 (1) or I8 with block scales (2), quantized by the
     oracle's definition of the formats; 3 is F16 in the kernels' two-cell
-    bricks of large grids."""
+    bricks of large grids; `walk` runs the build whose march falls back to
+    the cell walk after 4 iterations."""
     rays_soa = np.ascontiguousarray(rays_soa, dtype=np.float32)
     n = rays_soa.shape[1]
     N = 0 if grid is None else np.asarray(grid).shape[-1]
@@ -82,7 +88,7 @@ def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, cert
         arrays.append(np.asarray(tmax_ray, np.float32))
     hdr = [0, n, len(verts), len(tris), N, (tmin is not None) | (2 if tmax_ray is not None else 0), mode, fmt]
     par = [tmax, tau, g4[0], g4[1], g4[2], g4[3], 1.0 if certified else 0.0, tau_end]
-    raw = _run(hdr, par, arrays, 4 * n * 7)
+    raw = _run(hdr, par, arrays, 4 * n * 7, walk=walk)
     t = raw[: 4 * n].view(np.float32)
     prim = raw[4 * n: 8 * n].view(np.int32)
     u = raw[8 * n: 12 * n].view(np.float32)

@@ -76,6 +76,33 @@ def test_tiny_pure_and_limits(hyb, orc, tiny, tiny_dev, which):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_tiny_inflated_bound(hyb, orc, tiny, tiny_dev, fmt):
+    """One extreme sample far outside the room (1000 at node (0, 0, 0)) makes
+    the grid's bounds huge (L about 4.7e4): every sphere step would be a tiny
+    fraction of a cell, so the march takes cell steps and still ends at the
+    oracle's first root on every decided ray, within one fetch per crossed
+    cell and without NaN; the voxel size reported is the grid's h."""
+    sc, g4 = tiny["scene"], tiny["grid4"]
+    grid = tiny["grid"].copy()
+    grid.reshape(-1)[0] = 1000.0
+    sdf = hyb.sdf_from_grid(to_dev(grid.reshape(-1)), g4, fmt=fmt)
+    assert sdf.lipschitz > 1e4 and sdf.h == g4[3]
+    deq = orc.quantize(grid, fmt)[0] if fmt else grid
+    N = grid.shape[0]
+    for which in ("free", "surf"):
+        s = tiny[which].soa()
+        for tau in (0.0, 1.0):
+            got = host(hyb.trace(tiny_dev["bvh"], sdf, tiny_dev[which], 2.0, tau))
+            ref = orc.query(sc.verts, sc.tris, deq, g4, s, 2.0, tau)
+            m, c = orc.margin(sc.verts, sc.tris, deq, g4, s, 2.0, tau)
+            st = parity.check(got, ref, m, c, label="gpu outlier fmt %d %s tau=%s" % (fmt, which, tau))
+            assert not np.isnan(got[0]).any()
+            print("outlier", fmt, which, tau, st)
+        (_, prim, _, _), cnt = hyb.trace_counters(tiny_dev["bvh"], sdf, tiny_dev[which], 2.0, 0.0, hyb.MODE_DF)
+        assert cnt.cpu().numpy()[:, 2].max() <= 3 * N
+
+
 def test_tiny_counters_early_exit(hyb, tiny_dev):
     (t, prim, u, v), cnt = hyb.trace_counters(tiny_dev["bvh"], tiny_dev["sdf"], tiny_dev["surf"], 2.0, 2.0)
     prim, cnt = prim.cpu().numpy(), cnt.cpu().numpy()

@@ -73,9 +73,10 @@ def test_update_rejects_bad_input(hyb, tiny, grids):
     assert L.hyb_sdf_update(None, hyb._ptr(_dev(g1.reshape(-1))), 0, None) == 1
     assert L.hyb_sdf_update(a.handle, None, 0, None) == 1
     assert L.hyb_sdf_update(a.handle, hyb._ptr(_dev(g1.reshape(-1))), ctypes.c_uint32(0x80), None) == 1
-    bad = g1.copy()
-    bad[3, 4, 5] = np.inf
-    assert L.hyb_sdf_update(a.handle, hyb._ptr(_dev(bad.reshape(-1))), 0, None) == 1
+    for v in (np.inf, -np.inf, np.nan):
+        bad = g1.copy()
+        bad[3, 4, 5] = v
+        assert L.hyb_sdf_update(a.handle, hyb._ptr(_dev(bad.reshape(-1))), 0, None) == 1
     with pytest.raises(ValueError):
         hyb.sdf_update(a, _dev(g1.reshape(-1)[:-1]))
     # a later valid update restores the handle
@@ -108,3 +109,54 @@ def test_autograd_with_updated_handle(hyb, tiny, grids):
         scale = np.abs(res[0][1]).max()
         assert scale > 0
         np.testing.assert_allclose(res[0][1], res[1][1], rtol=1e-5, atol=1e-6 * scale)
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_non_finite_samples_rejected(hyb, tiny, grids, fmt):
+    """A NaN or infinite sample is an error in every format: the FP32 bound
+    pass drops NaN from its maxima, and the compact formats would turn it into
+    a finite code, so the samples are tested on their own."""
+    g1, _ = grids
+    L = hyb.lib()
+    a = hyb.sdf_from_grid(_dev(g1.reshape(-1)), tiny["grid4"], fmt=fmt)
+    for v in (np.nan, np.inf, -np.inf):
+        bad = g1.copy()
+        bad[7, 2, 30] = v
+        out = ctypes.c_void_p()
+        g4 = np.ascontiguousarray(tiny["grid4"], np.float32)
+        assert L.hyb_sdf_from_grid(hyb._ptr(_dev(bad.reshape(-1))), g1.shape[0], g4.ctypes.data_as(ctypes.c_void_p),
+                                   0, fmt, None, ctypes.byref(out)) == 1
+        assert L.hyb_sdf_update(a.handle, hyb._ptr(_dev(bad.reshape(-1))), 0, None) == 1
+    if fmt == 1:
+        # beyond the half range: +inf once stored
+        big = g1.copy()
+        big[0, 0, 0] = 1e6
+        assert L.hyb_sdf_update(a.handle, hyb._ptr(_dev(big.reshape(-1))), 0, None) == 1
+
+
+def test_batch_follows_update(hyb, tiny, grids):
+    """A batch holding a handle that hyb_sdf_update changes uses the new
+    samples and step bounds (a grid with an inflated bound and without the
+    certification) at its next launch: every result equal to hyb_trace on the
+    updated handle, eagerly and as a graph."""
+    g1, g2 = grids
+    sc = tiny["scene"]
+    bvh = hyb.build_bvh(sc.verts, sc.tris)
+    R = _dev(tiny["surf"].soa())
+    n = R.shape[1]
+    sdf = hyb.sdf_from_grid(_dev(g1.reshape(-1)), tiny["grid4"], lipschitz_samples=True)
+    out = hyb.alloc_hits(n)
+    batch = hyb.Batch([dict(bvh=bvh, sdf=sdf, rays=R, out=out, tmax=TMAX, threshold=1.0)])
+    batch.launch()
+    g3 = g2.copy()
+    g3[0, 0, 0] = 1000.0  # one extreme sample: L grows by four orders of magnitude
+    for g in (g3, g2):
+        hyb.sdf_update(sdf, _dev(g.reshape(-1)))
+        ref = [x.cpu().numpy() for x in hyb.trace(bvh, sdf, R, TMAX, 1.0)]
+        for graph in (False, True):
+            for x in out:
+                x.fill_(7)
+            batch.launch(graph=graph)
+            got = [x.cpu().numpy() for x in out]
+            for k, (x, y) in enumerate(zip(got, ref)):
+                assert np.array_equal(x, y), (graph, k)

@@ -210,3 +210,53 @@ def test_block_order_eighths(emu):
         for x in range(8):
             mine = order[x:nb // 8 * 8:8]
             assert np.array_equal(mine, np.arange(x * (nb // 8), (x + 1) * (nb // 8)))
+
+
+def outlier_grid(tiny):
+    """The tiny room's exact grid with one far corner sample, outside the room
+    and off every ray's path, set to 1000: the grid's Lipschitz bound grows
+    from sqrt(3) to about 4.7e4, so every certified sphere step shrinks to a
+    tiny fraction of a cell."""
+    g = tiny["grid"].copy()
+    g.reshape(-1)[0] = 1000.0
+    return g
+
+
+@pytest.mark.parametrize("walk", [False, True])
+@pytest.mark.parametrize("tau", [0.0, 1.0])
+def test_inflated_bound_still_exact(emu, orc, tiny, tau, walk):
+    """A grid whose bound is inflated by one extreme sample is traced exactly:
+    the march takes cell steps where sphere steps would be short, so every ray
+    ends within about one fetch per crossed cell.  walk: the build whose
+    march falls back to the cell-by-cell walk after 4 iterations (the path a
+    ray takes when its mixed march runs out of iterations) gives the same
+    classes and the oracle's roots."""
+    sc, g4 = tiny["scene"], tiny["grid4"]
+    grid = outlier_grid(tiny)
+    assert orc.lipschitz(grid, np.float64(g4[3])) > 1e4
+    N = grid.shape[0]
+    for rays in (tiny["free"], tiny["surf"]):
+        got = emu.trace(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, tau, walk=walk)
+        ref = orc.query(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, tau)
+        m, c = orc.margin(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, tau)
+        parity.check(got, ref, m, c, label="emu outlier tau=%s walk=%s" % (tau, walk))
+        assert not np.isnan(got[0]).any()
+        # at most the cells a segment crosses (3 (N - 2) + 1) plus one fetch
+        # per sphere step and per return to the verified point
+        assert got[4][:, 2].max() <= 3 * N
+
+
+@pytest.mark.parametrize("certified", [False, True])
+def test_walk_fallback_matches_march(emu, tiny, certified):
+    """On the exact grid, the walk-only fall-back finds the same first roots
+    as the full march (same classes, t within a few FP32 ulps of the root
+    refinement), with more fetches."""
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    for rays in (tiny["free"], tiny["surf"]):
+        a = emu.trace(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, 0.0, mode=2, certified=certified)
+        b = emu.trace(sc.verts, sc.tris, grid, g4, rays.soa(), 2.0, 0.0, mode=2, certified=certified, walk=True)
+        assert np.array_equal(a[1], b[1])
+        hit = np.isfinite(a[0])
+        assert np.array_equal(hit, np.isfinite(b[0]))
+        assert np.all(np.abs(a[0][hit] - b[0][hit]) <= 1e-6 * np.maximum(a[0][hit], 0.05))
+        assert b[4][:, 2].sum() > a[4][:, 2].sum()

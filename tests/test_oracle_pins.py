@@ -580,3 +580,239 @@ def test_shadow_limits_and_decomposition(orc, tiny):
     er, et = W.shadow_rays(pts, np.tile([0, 1.0, 0], (256, 1)), 3)
     r = orc.query(empty.verts, empty.tris, eg, g4, er.soa(), 10.0, 1.0, mode=3, tmax_ray=et, tau_end=1.0)
     assert np.all(r[1] == -1)
+
+
+# ---------------------------------------------------------------------------
+# Lipschitz bound of the interpolant (the safe-step bound)
+# ---------------------------------------------------------------------------
+
+def node_grid(N, g4, fn):
+    """Samples fn(X, Y, Z) at the nodes lo + (i, j, k) h, indexed [k, j, i]."""
+    x = np.float64(g4[0]) + np.arange(N) * np.float64(g4[3])
+    y = np.float64(g4[1]) + np.arange(N) * np.float64(g4[3])
+    z = np.float64(g4[2]) + np.arange(N) * np.float64(g4[3])
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return fn(X, Y, Z)
+
+
+def test_lipschitz_of_linear_field_is_its_gradient_norm(orc):
+    """Every cell of a linear field a.p + b has edge differences a_i h along
+    axis i, so the bound is |a| exactly (a dropped square root or a missing
+    1/h would not give it)."""
+    g4 = np.array([0.0, 0.0, 0.0, 0.125], np.float32)
+    for a in ([0.3, -0.7, 0.2], [2.0, 0.0, 0.0], [0.0, 0.0, -5.5], [1.0, 1.0, 1.0]):
+        a = np.array(a)
+        grid = node_grid(9, g4, lambda X, Y, Z: a[0] * X + a[1] * Y + a[2] * Z + 0.4)
+        assert abs(orc.lipschitz(grid, 0.125) - np.linalg.norm(a)) <= 1e-12 * max(1.0, np.linalg.norm(a))
+
+
+def test_lipschitz_of_corner_distance_is_sqrt3(orc):
+    """Distance to the last node c of the grid: the only cell with c as a
+    corner has |x-, y- and z-edge differences| of exactly h on the three edges
+    through c (the edges of its far corner), every other edge difference is
+    smaller (triangle inequality), so the bound is sqrt(3).  A bound that
+    looked at fewer than the four edges per axis of a cell gives less."""
+    N, h = 10, 0.1
+    g4 = np.array([0.0, 0.0, 0.0, h], np.float32)
+    c = np.float64(g4[0]) + (N - 1) * np.float64(g4[3])
+    grid = node_grid(N, g4, lambda X, Y, Z: np.sqrt((X - c) ** 2 + (Y - c) ** 2 + (Z - c) ** 2))
+    assert abs(orc.lipschitz(grid, np.float64(g4[3])) - math.sqrt(3)) <= 1e-12
+    # distance to the first node: the same bound, attained at the first cell
+    grid = node_grid(N, g4, lambda X, Y, Z: np.sqrt(X ** 2 + Y ** 2 + Z ** 2))
+    assert abs(orc.lipschitz(grid, np.float64(g4[3])) - math.sqrt(3)) <= 1e-12
+
+
+def test_lipschitz_bounds_and_attains_the_interpolant_slope(orc):
+    """A single sample v in a zero grid: the interpolant's gradient at that
+    node, inside each of its 8 cells, has norm sqrt(3) |v| / h, the bound; and
+    no slope between sampled point pairs exceeds it."""
+    N, h, v = 7, 0.2, -0.9
+    g4 = np.array([0.0, 0.0, 0.0, h], np.float32)
+    grid = np.zeros((N, N, N))
+    grid[3, 2, 4] = v
+    L = orc.lipschitz(grid, np.float64(g4[3]))
+    assert abs(L - math.sqrt(3) * abs(v) / np.float64(g4[3])) <= 1e-12 * L
+    node = np.array([4, 2, 3]) * np.float64(g4[3])
+    eps = 1e-7
+    for s in np.array(np.meshgrid([-1, 1], [-1, 1], [-1, 1])).T.reshape(-1, 3):
+        p = node + 1e-3 * s
+        g = np.array([(orc.df_value(grid, g4, p + eps * e) - orc.df_value(grid, g4, p - eps * e)) / (2 * eps)
+                      for e in np.eye(3)])
+        assert abs(np.linalg.norm(g) - L) <= 2e-2 * L
+    rng = np.random.default_rng(3)
+    p = rng.uniform(0, (N - 1) * h, size=(4000, 3))
+    q = p + rng.normal(scale=0.05, size=p.shape)
+    q = np.clip(q, 0, (N - 1) * h)
+    f = orc.df_values(grid, g4, np.concatenate([p, q]))
+    slope = np.abs(f[:4000] - f[4000:]) / np.maximum(np.linalg.norm(p - q, axis=1), 1e-12)
+    assert slope.max() <= L * (1 + 1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Margins: the distance of each ray from the decisions of the query
+# ---------------------------------------------------------------------------
+
+HAND = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+
+
+def tri_margin(orc, verts, tris, o, d, a, b):
+    v = np.asarray(verts, np.float32)
+    m, c = orc.margin(v, np.asarray(tris, np.int32), None, None, soa(o, d), b, 0.0, mode=orc.MODE_BVH,
+                      tmin=np.full(len(np.atleast_2d(o)), a, np.float32))
+    return m, c
+
+
+def test_margin_distance_to_the_winners_edge(orc):
+    """A ray along the hand triangle's normal through the in-plane point
+    (0.3, delta): the nearest edge is y = 0 at distance delta, and the t gaps
+    (to a = 0: 1 / 0.05; to b = 10: 9 / 10) are larger, so the margin is
+    delta; the conditioning is |d . n| = 1."""
+    for delta in (1e-3, 0.02, 0.1):
+        m, c = tri_margin(orc, HAND, [[0, 1, 2]], [0.3, delta, 1.0], [0, 0, -1], 0.0, 10.0)
+        assert abs(m[0] - np.float32(delta)) <= 1e-7 * delta and c[0] == 1.0
+    # inside near the hypotenuse: distance (1 - x - y) / sqrt(2)
+    x, y = np.float32(0.5), np.float32(0.45)
+    m, _ = tri_margin(orc, HAND, [[0, 1, 2]], [x, y, 1.0], [0, 0, -1], 0.0, 10.0)
+    assert abs(m[0] - (1 - np.float64(x) - np.float64(y)) / math.sqrt(2)) <= 1e-12
+    # a tilted ray on a triangle twice the size (|e1 x e2| = 4): conditioning
+    # |d . n| / |n| = |d_z|
+    d = W._normalize32(np.array([[0.6, 0.0, -0.8]]))[0]
+    _, c = tri_margin(orc, 2 * HAND, [[0, 1, 2]], [-0.5, 0.2, 1.0], d, 0.0, 10.0)
+    assert abs(c[0] - abs(np.float64(d[2]))) <= 1e-12
+
+
+def test_margin_of_a_near_miss(orc):
+    """A ray that passes delta outside the edge y = 0 misses; its margin is
+    the distance of the line from that edge."""
+    for delta in (1e-4, 0.01, 0.05):
+        m, c = tri_margin(orc, HAND, [[0, 1, 2]], [0.3, -delta, 1.0], [0, 0, -1], 0.0, 10.0)
+        assert abs(m[0] - np.float32(delta)) <= 1e-7 * delta and c[0] == 1.0
+    # beyond a vertex the nearest boundary point is the vertex itself
+    m, _ = tri_margin(orc, HAND, [[0, 1, 2]], [-0.03, -0.04, 1.0], [0, 0, -1], 0.0, 10.0)
+    assert abs(m[0] - 0.05) <= 1e-8
+
+
+def test_margin_of_the_gap_to_the_next_hit_and_the_interval_ends(orc):
+    """Two parallel triangles at t = 1 and t = 1 + g on the ray: the relative
+    gap g / max(t, 0.05) to the next hit decides; a segment end just past the
+    hit gives its relative gap instead."""
+    v = np.concatenate([HAND, HAND - np.float32([0, 0, 0.004])])
+    tris = [[0, 1, 2], [3, 4, 5]]
+    g = -np.float64(np.float32(-0.004))  # the second plane's z as stored in FP32
+    m, _ = tri_margin(orc, v, tris, [0.25, 0.25, 1.0], [0, 0, -1], 0.0, 10.0)
+    assert abs(m[0] - g) <= 1e-12
+    # only the winner inside [a, b]: the gap to b = 1.002 (b and a are FP32)
+    b = np.float64(np.float32(1.002))
+    m, _ = tri_margin(orc, HAND, [[0, 1, 2]], [0.25, 0.25, 1.0], [0, 0, -1], 0.0, b)
+    assert abs(m[0] - (b - 1.0) / b) <= 1e-12
+    # and to a = 0.999 (relative to max(a, 0.05))
+    a = np.float64(np.float32(0.999))
+    m, _ = tri_margin(orc, HAND, [[0, 1, 2]], [0.25, 0.25, 1.0], [0, 0, -1], a, 10.0)
+    assert abs(m[0] - (1.0 - a) / a) <= 1e-12
+    # the second triangle inside the triangle but just past b: its gap to b
+    b = np.float64(np.float32(1.003))
+    m, _ = tri_margin(orc, v, tris, [0.25, 0.25, 1.0], [0, 0, -1], 0.0, b)
+    assert abs(m[0] - (1.0 + g - b) / b) <= 1e-12
+
+
+def df_margin(orc, grid, g4, o, d, a, b):
+    n = len(np.atleast_2d(o))
+    return orc.margin(None, np.zeros((0, 3), np.int32), grid, g4, soa(o, d), b, 0.0, mode=orc.MODE_DF,
+                      tmin=np.full(n, a, np.float32))
+
+
+def test_df_margin_segment_starting_inside(orc):
+    """A segment that starts where the interpolant is -s (a linear field, so
+    exact): the hit is the start itself and the margin is s / h."""
+    N, h = 16, 0.0625
+    g4 = np.array([0.0, 0.0, 0.0, h], np.float32)
+    grid = node_grid(N, g4, lambda X, Y, Z: Z - 0.5)
+    for s in (0.002, 0.01, 0.03):
+        o = np.array([0.4, 0.45, 0.5 - s], np.float32)
+        m, c = df_margin(orc, grid, g4, o, [0.6, 0.0, 0.8], 0.0, 0.5)
+        sz = 0.5 - np.float64(o[2])
+        assert abs(m[0] - sz / h) <= 1e-9 and c[0] == 1.0
+        assert orc.df_hit(grid, g4, soa(o, [0.6, 0.0, 0.8]), 0.0, 0.5)[0] == 0.0
+
+
+def test_df_margin_local_minimum_of_a_grazing_ray(orc):
+    """The bilinear field kappa (x - x0)(y - y0) + m0 is reproduced exactly by
+    the trilinear interpolant.  Along d = (1, 1, 0)/sqrt(2) from
+    (x0 - s, y0 - s, z) it is m0 + kappa (t/sqrt(2) - s)^2: no root, one
+    local minimum m0, so the margin is m0 / h; with m0 < 0 the hit is the
+    first root and the margin is the relative gap to b or the slope."""
+    N, h = 24, 0.05
+    g4 = np.array([0.0, 0.0, 0.0, h], np.float32)
+    x0, y0, kappa = 0.52, 0.47, 3.0
+    d = np.array([1.0, 1.0, 0.0]) / math.sqrt(2)
+    o = np.array([x0 - 0.3, y0 - 0.3, 0.6], np.float32)
+    d32 = d.astype(np.float32)
+    # the ray in FP64 as the oracle reads it: s along each axis, unit speed
+    s_x = x0 - np.float64(o[0])
+    assert abs(s_x - (y0 - np.float64(o[1]))) < 1e-7
+    for m0 in (1e-4, 2e-3, 0.01):
+        grid = node_grid(N, g4, lambda X, Y, Z: kappa * (X - x0) * (Y - y0) + m0)
+        m, c = df_margin(orc, grid, g4, o, d32, 0.0, 0.8)
+        assert np.isinf(orc.df_hit(grid, g4, soa(o, d32), 0.0, 0.8)[0])
+        assert abs(m[0] - m0 / np.float64(g4[3])) <= 1e-6 * max(1.0, m0 / h) and c[0] == 1.0
+    # below zero at the minimum: the first root t* = sqrt(2) (s - sqrt(-m0 /
+    # kappa)) decides, with margin (b - t*) / b and conditioning |g'(t*)| =
+    # sqrt(2) sqrt(-m0 kappa) (the slope at the root, not at the cell entry)
+    for m0 in (-2e-3, -0.01):
+        grid = node_grid(N, g4, lambda X, Y, Z: kappa * (X - x0) * (Y - y0) + m0)
+        dd = d32.astype(np.float64)
+        ox, oy = np.float64(o[0]), np.float64(o[1])
+        # kappa (ox - x0 + t dx)(oy - y0 + t dy) + m0 = 0, first root
+        A = kappa * dd[0] * dd[1]
+        B = kappa * ((ox - x0) * dd[1] + (oy - y0) * dd[0])
+        C = kappa * (ox - x0) * (oy - y0) + m0
+        ts = (-B - math.sqrt(B * B - 4 * A * C)) / (2 * A)
+        assert abs(ts - math.sqrt(2) * (s_x - math.sqrt(-m0 / kappa))) < 1e-6
+        t = orc.df_hit(grid, g4, soa(o, d32), 0.0, 0.8)[0]
+        assert abs(t - ts) <= 1e-12
+        m, c = df_margin(orc, grid, g4, o, d32, 0.0, 0.8)
+        b = np.float64(np.float32(0.8))
+        assert abs(m[0] - (b - ts) / b) <= 1e-12
+        assert abs(c[0] - abs(2 * A * ts + B)) <= 1e-9 and abs(c[0] - math.sqrt(2) * math.sqrt(-m0 * kappa)) < 1e-5
+
+
+def test_df_margin_of_a_hit_near_the_segment_end(orc):
+    """A plane hit at t* with the segment ending at b just past it: the
+    relative gap (b - t*) / max(b, 0.05) is the margin, and the conditioning
+    is |g'(t*)| = |n . d|."""
+    N, h = 16, 0.0625
+    g4 = np.array([0.0, 0.0, 0.0, h], np.float32)
+    nrm = np.array([0.0, 0.6, 0.8])
+    grid = node_grid(N, g4, lambda X, Y, Z: 0.5 - nrm[1] * Y - nrm[2] * Z)  # positive at o, falling along d
+    o = np.array([0.3, 0.1, 0.1], np.float32)
+    d = W._normalize32(np.array([[0.2, 0.5, 0.7]]))[0]
+    od, dd = o.astype(np.float64), d.astype(np.float64)
+    ts = (0.5 - nrm @ od) / (nrm @ dd)
+    for gap in (1e-3, 1e-2):
+        b = np.float32(ts + gap)
+        m, c = df_margin(orc, grid, g4, o, d, 0.0, b)
+        assert abs(m[0] - (np.float64(b) - ts) / np.float64(b)) <= 1e-9
+        assert abs(c[0] - abs(nrm @ dd)) <= 1e-12
+
+
+def test_combined_margin_composes_the_two_parts(orc):
+    """Combined query (threshold 1 voxel): a ray whose triangle segment hits
+    takes the triangle margin alone; a ray whose triangle segment misses takes
+    the smaller of its triangle terms and its distance-field margin."""
+    N, h = 16, 0.0625
+    g4 = np.array([0.0, 0.0, 0.0, h], np.float32)
+    grid = node_grid(N, g4, lambda X, Y, Z: Z - 0.3)  # a plane the DF part hits
+    v = (HAND * np.float32(0.5) + np.float32([0.2, 0.2, 0.7]))
+    d = np.array([0, 0, -1], np.float32)
+    # hits the triangle 0.01 below the origin, 0.03 inside its edge y = 0.2
+    o1 = np.array([0.3, 0.23, 0.71], np.float32)
+    m, _ = orc.margin(v, [[0, 1, 2]], grid, g4, soa(o1, d), 1.0, 1.0)
+    mt, _ = tri_margin(orc, v, [[0, 1, 2]], o1, d, 0.0, np.float32(h))
+    assert m[0] == mt[0] and abs(m[0] - (np.float64(o1[1]) - 0.2)) <= 1e-7
+    # starts below the triangle: the triangle segment misses, the DF part hits
+    # the plane at 0.4; the DF margin (gap to b) and the triangle terms compete
+    o2 = np.array([0.3, 0.23, 0.69], np.float32)
+    m, c = orc.margin(v, [[0, 1, 2]], grid, g4, soa(o2, d), 1.0, 1.0)
+    mt, _ = tri_margin(orc, v, [[0, 1, 2]], o2, d, 0.0, np.float32(h))
+    md, cd = df_margin(orc, grid, g4, o2, d, np.float32(h), 1.0)
+    assert m[0] == min(mt[0], md[0]) and c[0] == cd[0] == 1.0
