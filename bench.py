@@ -29,6 +29,33 @@ sys.path.insert(0, ROOT)
 TAUS = (0.0, 0.5, 1.0, 2.0, 4.0, math.inf)
 TMAX = 0.5
 HBM_PEAK_GBS = 8000.0
+# Vector ALU issue rate of one MI355X: 256 compute units x 4 SIMDs x 16 lanes
+# x 2.4 GHz, one unpacked FP32 (or integer) lane operation per lane and clock
+# (a wave64 instruction issues over 4 clocks); an FMA counts as one operation.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+N_SIMD, CLOCK_HZ = 256 * 4, 2.4e9
+
+# Algorithmic work per unit of the path (the traversal and march themselves):
+# bytes moved and VALU lane operations per four-wide BVH node visited (four
+# boxes of 24 B + four child references; four slab tests), per triangle tested
+# (48 B; the watertight test), per distance-field fetch (8 FP32 corners; the
+# trilinear value and the step), plus 24 B of ray in and 16 B of hit out.
+BYTES_RAY, BYTES_NODE, BYTES_TRI, BYTES_FETCH = 40.0, 128.0, 48.0, 32.0
+OPS_NODE, OPS_TRI, OPS_FETCH = 48.0, 35.0, 30.0
+
+# The paper's own measurements (Fig. 1 and Fig. 2; AMD Radeon RX 6800 XT,
+# DX12/DXR research renderer, resolution and ray counts not stated): context,
+# not targets, and not comparable per ray.
+PAPER = {
+    "hardware": "AMD Radeon RX 6800 XT (hardware ray tracing), DX12/DXR; resolution and ray count not stated",
+    "gi10_frame_ms": {"hwrt_only": 5.66, "combined": 4.55, "df_only": 3.58, "source": "Fig. 1"},
+    "ao_tracing_ms": [
+        {"scene": "Bistro, AO distance 100", "hwrt_only": 8.33, "combined": 3.16, "df_only": 1.35, "source": "Fig. 2"},
+        {"scene": "simpler scene, AO distance 10", "hwrt_only": 2.73, "combined": 1.86, "df_only": 1.13,
+         "source": "Fig. 2"},
+        {"scene": "simpler scene, AO distance 10", "hwrt_only": 1.72, "combined": 1.64, "df_only": 1.14,
+         "source": "Fig. 2"}],
+}
 
 
 def log(*a):
@@ -66,17 +93,50 @@ def source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(tau):
-    """HBM bytes per launch of the combined kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source at
-    this threshold; else None."""
-    f = os.path.join(ROOT, "profiles", "traffic_gi1080p.json")
+def measured_counters(tau):
+    """Counters per launch of the GI query at this threshold from the
+    committed rocprofv3 summary (profiles/counters_gi1080p.json), if they were
+    taken on the current kernel source; else None."""
+    f = os.path.join(ROOT, "profiles", "counters_gi1080p.json")
     if not os.path.exists(f):
         return None
     rec = json.load(open(f))
-    if rec.get("source_sha256") != source_sha256() or rec.get("threshold") != tau:
+    if rec.get("source_sha256") != source_sha256():
         return None
-    return rec["read_bytes"] + rec["write_bytes"]
+    key = "inf" if math.isinf(tau) else repr(float(tau))
+    return rec.get("thresholds", {}).get(key)
+
+
+def work_model(c):
+    """Algorithmic bytes and VALU lane operations per ray from mean counts
+    (four-wide nodes, triangles, distance-field fetches)."""
+    b = BYTES_RAY + BYTES_NODE * c[0] + BYTES_TRI * c[1] + BYTES_FETCH * c[2]
+    ops = OPS_NODE * c[0] + OPS_TRI * c[1] + OPS_FETCH * c[2]
+    return b, ops
+
+
+def roofline(c, n, ms, tau):
+    """Roofline of one query launch: the VALU roof (the kernels issue-bound
+    under divergence, which the counters show) with the HBM figures beside it;
+    `traffic` and the issue model come from the committed counters when they
+    match the source."""
+    b, ops = work_model(c)
+    sec = ms * 1e-3
+    alu = ops * n / sec / 1e12
+    gbs = b * n / sec / 1e9
+    prof = measured_counters(tau)
+    r = {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (VALU lane operations)",
+         "frac": alu / VALU_PEAK_TOPS, "traffic": None if prof is None else prof["read_bytes"] + prof["write_bytes"],
+         "ops_per_ray": ops, "bytes_per_ray": b, "nodes_per_ray": float(c[0]), "tris_per_ray": float(c[1]),
+         "df_fetches_per_ray": float(c[2]),
+         "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}}
+    if prof is not None:
+        issue_s = prof["valu_insts"] * 4.0 / N_SIMD / CLOCK_HZ
+        r["issue"] = {"valu_insts_per_launch": prof["valu_insts"], "valu_issue_us": issue_s * 1e6,
+                      "valu_issue_frac_of_launch": issue_s / (prof["kernel_us"] * 1e-6),
+                      "lane_utilisation": prof["lane_utilisation"], "l2_hit": prof["l2_hit"],
+                      "kernel": prof["kernel"], "profile_kernel_us": prof["kernel_us"]}
+    return r
 
 
 def cpu_model():
@@ -129,6 +189,8 @@ def main():
     ap.add_argument("--scenes", type=int, default=64, help="batch config: number of scenes")
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="gi config: skip the GPU timings of the shadow, refit, precision and batch workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the ray query shards by rays with no exchange step; "
@@ -223,13 +285,15 @@ def main():
     tau = math.inf if chosen["tau"] == "inf" else chosen["tau"]
 
     # work counters at the chosen threshold -> algorithmic bytes per ray
-    (_, _, _, _), cnt = hyb.trace_counters(bvh, sdf128, R, TMAX, tau, hyb.MODE_COMBINED)
-    c = cnt.double().mean(dim=0).cpu().numpy()
-    cnt_np = cnt.cpu().numpy()
-    work = {name: {"mean": float(cnt_np[:, k].mean()), "p50": float(np.percentile(cnt_np[:, k], 50)),
+    def counts(t):
+        (_, _, _, _), cnt = hyb.trace_counters(bvh, sdf128, R, TMAX, t, hyb.MODE_COMBINED)
+        cnt_np = cnt.cpu().numpy()
+        return cnt.double().mean(dim=0).cpu().numpy(), {
+            name: {"mean": float(cnt_np[:, k].mean()), "p50": float(np.percentile(cnt_np[:, k], 50)),
                    "p99": float(np.percentile(cnt_np[:, k], 99)), "max": int(cnt_np[:, k].max())}
             for k, name in enumerate(("bvh_nodes", "triangles", "df_fetches"))}
-    bytes_per_ray = 24 + 16 + 128 * c[0] + 48 * c[1] + 32 * c[2]
+
+    c, work = counts(tau)
 
     # timed region: K steps of the combined query at the chosen threshold
     for _ in range(args.warmup):
@@ -254,7 +318,18 @@ def main():
     wall = time.time() - wall0
     ms_step = start.elapsed_time(stop) / args.steps
     value = n / ms_step / 1e3  # Mrays/s
-    achieved = bytes_per_ray * n / (ms_step * 1e-3) / 1e9
+
+    # the combined query that runs both techniques on every ray (threshold 1
+    # voxel): its own time, work, roofline and error
+    s1 = next(s for s in sweep if s["tau"] == 1.0)
+    c1, work1 = counts(1.0)
+    ms1 = time_launches(lambda: hyb.trace(bvh, sdf128, R, TMAX, 1.0, out=out), stream, args.steps, args.warmup)
+    combined_tau1 = {"threshold": 1.0, "ms": ms1, "mrays_s": n / ms1 / 1e3, "speedup_vs_bvh_only": ms_bvh / ms1,
+                     "artefact_rate": s1["rate"], "mean_dp_over_h": s1["mean_dp_over_h"],
+                     "roofline": roofline(c1, n, ms1, 1.0), "work_per_ray": work1}
+    log("tau=1: %.3f ms, ALU frac %.3f, HBM frac %.3f" % (ms1, combined_tau1["roofline"]["frac"],
+                                                          combined_tau1["roofline"]["hbm"]["frac"]))
+    extras = run_extras(args, torch, hyb, W, dev, stream, scene, gb, bvh, g128) if args.extras else None
 
     cpu = None
     if args.cpu_sample > 0:
@@ -301,11 +376,9 @@ def main():
                                "diffuse rays (%d), tmax 0.5, threshold %s voxels" % (
                                    scene.n_tris, args.width, args.height, n, chosen["tau"]),
                    "rays": n, "triangles": scene.n_tris, "grid": 128, "tmax": TMAX, "threshold": chosen["tau"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(tau),
-                     "bytes_per_ray": bytes_per_ray, "nodes_per_ray": c[0], "tris_per_ray": c[1],
-                     "df_fetches_per_ray": c[2]},
+        "roofline": roofline(c, n, ms_step, tau),
         "cpu_baseline": cpu,
+        "combined_tau1": combined_tau1,
         "bvh_only": {"ms": ms_bvh, "mrays_s": n / ms_bvh / 1e3},
         "df_only": df_only,
         "sweep": sweep,
@@ -313,8 +386,122 @@ def main():
         "speedup_vs_bvh_only": ms_bvh / ms_step,
         "work_per_ray": work,
         "timed_wall_s": wall,
+        "extras": extras,
+        "paper": PAPER,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_extras(args, torch, hyb, W, dev, stream, scene, gb, bvh, g128):
+    """GPU timings of the other workloads (no oracle): shadow rays and the
+    refit step on the GI scene, the 256^3 precision workload in three storage
+    formats, and the 64-scene batch in one graph launch."""
+    t0 = time.time()
+    ex = {}
+    sdf = hyb.build_sdf(bvh, 128, g128)
+    h = float(g128[3])
+    # shadow rays to an area light: thresholds (1, 1) against exact any-hit triangles
+    srays, stmax = W.shadow_rays(gb.p, gb.n, 22)
+    RS, TS = torch.from_numpy(srays.soa()).to(dev), torch.from_numpy(stmax).to(dev)
+    out = hyb.alloc_hits(srays.n)
+    ms_ref = time_launches(lambda: hyb.trace_shadow(bvh, sdf, RS, 10.0, math.inf, math.inf, tmax_ray=TS, out=out),
+                           stream, args.reps, 2)
+    ref = out[1].cpu().numpy() != -1
+    ms_s = time_launches(lambda: hyb.trace_shadow(bvh, sdf, RS, 10.0, 1.0, 1.0, tmax_ray=TS, out=out), stream,
+                         args.reps, 2)
+    occ = out[1].cpu().numpy() != -1
+    ex["shadow"] = {"workload": "%d shadow rays from the GI G-buffer to a 0.3 x 0.3 area light, any hit" % srays.n,
+                    "thresholds": [1.0, 1.0], "ms": ms_s, "mrays_s": srays.n / ms_s / 1e3,
+                    "triangles_anyhit_ms": ms_ref, "speedup": ms_ref / ms_s,
+                    "occlusion_mismatch": float((occ != ref).mean())}
+    log("extras: shadow %.3f ms vs %.3f ms (%.1fs)" % (ms_s, ms_ref, time.time() - t0))
+
+    # refit: forward, backward and one Adam step on a learnable 128^3 grid
+    from paper_2305_07253_amd.autograd import df_hit
+    gbr = W.gbuffer(scene, 1024, 1024)
+    rr = W.rebias(W.gbuffer_rays(gbr, 41), gbr, h)
+    RR = torch.from_numpy(rr.soa()).to(dev)
+    target = hyb.trace_bvh(bvh, torch.from_numpy(W.gbuffer_rays(gbr, 41).soa()).to(dev), TMAX)[0]
+    goal = torch.where(torch.isfinite(target), target, torch.full_like(target, TMAX))
+    theta = hyb.sdf_read(sdf).reshape(-1).contiguous().clone().requires_grad_(True)
+    handle = hyb.sdf_from_grid(theta.detach().clone(), g128)
+    opt = torch.optim.Adam([theta], lr=0.002 * h)
+
+    def adam_step():
+        opt.zero_grad()
+        t = df_hit(theta, g128, RR, TMAX, sdf=handle)
+        use = torch.isfinite(t)
+        d = torch.where(use, t - goal, torch.zeros_like(t))
+        ((d * d).sum() / use.sum().clamp(min=1)).backward()
+        opt.step()
+
+    for _ in range(5):
+        adam_step()
+    torch.cuda.synchronize()
+    t1 = time.time()
+    for _ in range(20):
+        adam_step()
+    torch.cuda.synchronize()
+    step_ms = (time.time() - t1) * 1e3 / 20
+    o2 = hyb.alloc_hits(rr.n)
+    ms_fwd = time_launches(lambda: hyb.trace_df(handle, RR, TMAX, out=o2), stream, args.reps, 2)
+    grad = torch.zeros(128 ** 3, device=dev)
+    ones = torch.ones(rr.n, device=dev)
+    ms_bwd = time_launches(lambda: hyb.df_backward(handle, RR, TMAX, o2[0], ones, grad), stream, args.reps, 2)
+    ex["refit"] = {"workload": "128^3 FP32 learnable grid, %d G-buffer rays from p + h n, loss MSE vs triangle hits"
+                   % rr.n, "ms_per_adam_step": step_ms, "forward_kernel_ms": ms_fwd, "backward_kernel_ms": ms_bwd}
+    log("extras: refit step %.3f ms, fwd %.3f, bwd %.3f (%.1fs)" % (step_ms, ms_fwd, ms_bwd, time.time() - t0))
+    del theta, handle, opt, grad
+
+    # precision workload: 1.88M triangles, 256^3, 8.3M rays, three formats
+    ps = W.precision_scene(3)
+    g256 = W.room_grid(256)
+    prays = W.gbuffer_rays(W.gbuffer(ps, 1920, 1080), 31, spp=4)
+    pbvh = hyb.build_bvh(ps.verts, ps.tris)
+    f32 = hyb.build_sdf(pbvh, 256, g256)
+    vals = hyb.sdf_read(f32).reshape(-1).contiguous()
+    grids = {"f32": f32, "f16": hyb.sdf_from_grid(vals, g256, fmt=hyb.SDF_F16),
+             "i8": hyb.sdf_from_grid(vals, g256, fmt=hyb.SDF_I8_BRICK)}
+    del vals
+    PR = torch.from_numpy(prays.soa()).to(dev)
+    po = hyb.alloc_hits(prays.n)
+    prec = {"workload": "%d triangles, 256^3 grid, %d rays (4 per pixel at 1080p), tmax 0.5" % (ps.n_tris, prays.n)}
+    for tau in (0.0, 1.0):
+        for name, g in grids.items():
+            ms = time_launches(lambda: hyb.trace(pbvh, g, PR, TMAX, tau, out=po), stream, args.reps, 2)
+            prec["%s_tau%g_ms" % (name, tau)] = ms
+    prec["bvh_only_ms"] = time_launches(lambda: hyb.trace_bvh(pbvh, PR, TMAX, out=po), stream, args.reps, 2)
+    ex["precision"] = prec
+    log("extras: precision %s (%.1fs)" % (prec, time.time() - t0))
+    del grids, f32, pbvh, PR, po
+
+    # 64 scenes of uneven size in one persistent graph launch, autotuned
+    items, n_rays = [], 0
+    for sp in W.batch_specs(4, 64):
+        bs = W.batch_scene(sp)
+        bb = hyb.build_bvh(bs.verts, bs.tris)
+        brays = W.gbuffer_rays(W.gbuffer(bs, sp.width, sp.height), sp.seed)
+        items.append(dict(bvh=bb, sdf=hyb.build_sdf(bb, sp.n_grid, W.room_grid(sp.n_grid)),
+                          rays=torch.from_numpy(brays.soa()).to(dev), tmax=TMAX, threshold=1.0))
+        n_rays += brays.n
+    batch = hyb.Batch(items)
+    err, _ = batch.tune(max_error_rate=0.03, reps=3)
+    taus = [batch.threshold(k) for k in range(len(items))]
+    ms_graph = time_launches(lambda: batch.launch(), stream, args.reps, 2)
+
+    def per_scene():
+        for k, it in enumerate(items):
+            hyb.trace(it["bvh"], it["sdf"], it["rays"], TMAX, taus[k], out=batch.outs[k])
+
+    ms_loop = time_launches(per_scene, stream, args.reps, 2)
+    ex["batch"] = {"workload": "64 scenes (log-uniform 1k-500k triangles, %d rays in all), one graph launch, "
+                   "thresholds tuned per scene under a 3%% error cap" % n_rays, "ms_graph": ms_graph,
+                   "mrays_s": n_rays / ms_graph / 1e3, "ms_per_scene_launches": ms_loop,
+                   "speedup_vs_per_scene_launches": ms_loop / ms_graph, "error_rate_max": float(np.max(err)),
+                   "config": batch.config}
+    log("extras: batch %.3f ms vs %.3f ms per scene (%.1fs)" % (ms_graph, ms_loop, time.time() - t0))
+    ex["seconds"] = time.time() - t0
+    return ex
 
 
 def run_extra(args):

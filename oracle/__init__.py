@@ -290,3 +290,96 @@ def sdf_grid_sparse(scene, grid4, n, rays_o, rays_d, tmax, progress=None):
             progress("oracle samples: %d / %d nodes" % (c0, len(nodes)))
         grid[nodes[c0:c0 + step]] = sdf_nodes(scene, grid4, n, nodes=nodes[c0:c0 + step]).astype(np.float32)
     return grid.reshape(n, n, n), len(nodes)
+
+
+def _segment_cells(o, d, a, b, grid4, n, chunk=256):
+    """(ray index, cell) pairs covering every cell a segment o + t d, t in
+    [a_i, b_i], can cross: the points t = a_i + k h/8 <= b_i and, for each
+    point, the neighbouring cells across every face within h/8 of it.  (A
+    cell the segment enters after a point and before the next, or before b_i,
+    is entered within h/8 of that point, so it differs from the point's cell
+    only along axes whose face lies within h/8 of the point.)  The points of
+    [a, b'] are those of [a, b] up to b', so a shorter segment's cells are a
+    subset.  Cells are flat indices i + n (j + n k), clamped to [0, n - 2]."""
+    h = np.float64(grid4[3])
+    lo = np.asarray(grid4[:3], np.float64)
+    step, band = h / 8, 1.0 / 8 + 1e-9
+    o, d = np.asarray(o, np.float64), np.asarray(d, np.float64)
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    keys = []
+    for c0 in range(0, len(o), chunk):
+        sl = slice(c0, c0 + chunk)
+        aa, bb = a[sl], np.maximum(b[sl], a[sl])
+        if not len(aa):
+            continue
+        cnt = np.floor((bb - aa) / step).astype(np.int64) + 1  # points a + k step, k < cnt
+        m = int(cnt.max())
+        k = np.arange(m)[None, :]
+        keep = (k < cnt[:, None]).reshape(-1)
+        ts = aa[:, None] + k * step
+        x = ((o[sl, None, :] + ts[:, :, None] * d[sl, None, :] - lo) / h).reshape(-1, 3)[keep]
+        ray = np.repeat(np.arange(c0, c0 + len(aa), dtype=np.int64), m)[keep]
+        c = np.floor(x)
+        f = x - c
+        c = c.astype(np.int64)
+        for k in range(3):
+            lo_k, hi_k = f[:, k] < band, f[:, k] > 1.0 - band
+            cl, ch = c[lo_k].copy(), c[hi_k].copy()
+            cl[:, k] -= 1
+            ch[:, k] += 1
+            c = np.concatenate([c, cl, ch])
+            f = np.concatenate([f, f[lo_k], f[hi_k]])
+            ray = np.concatenate([ray, ray[lo_k], ray[hi_k]])
+        c = np.clip(c, 0, n - 2)
+        keys.append(np.unique(ray * (n ** 3) + c[:, 0] + n * (c[:, 1] + n * c[:, 2])))
+    if not keys:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    pair = np.unique(np.concatenate(keys))
+    return pair // (n ** 3), pair % (n ** 3)
+
+
+def _cell_nodes(cells, n):
+    ci, cj, ck = cells % n, (cells // n) % n, cells // (n * n)
+    return np.stack([(ci + dx) + n * ((cj + dy) + n * (ck + dz))
+                     for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)], axis=1)
+
+
+def sdf_grid_on_paths(scene, grid4, n, rays_soa, a, b, progress=None):
+    """Exact samples (sdf_nodes) at the nodes of every cell that each ray's
+    distance-field segment [a_i, b_i] crosses up to its first root, NaN
+    elsewhere, so that any read of another node shows.  Rays are extended
+    from a short reach, doubling it, until the first root that df_hit finds
+    on the sampled nodes lies beyond no unsampled cell (a root inside an
+    unsampled cell cannot be skipped unnoticed: the walk up to a later root
+    would cross that cell).  Returns (grid (n,n,n) float32, nodes computed)."""
+    r = np.ascontiguousarray(rays_soa, np.float32)
+    nr = r.shape[1]
+    o, d = r[:3].T.astype(np.float64), r[3:].T.astype(np.float64)
+    a = np.broadcast_to(np.asarray(a, np.float64), (nr,)).copy()
+    b = np.broadcast_to(np.asarray(b, np.float64), (nr,)).copy()
+    h = np.float64(grid4[3])
+    grid = np.full(n ** 3, np.nan, dtype=np.float32)
+    reach = np.full(nr, 8 * h)
+    pending = np.arange(nr)
+    computed = 0
+    while len(pending):
+        p = pending
+        ri, cells = _segment_cells(o[p], d[p], a[p], np.minimum(a[p] + reach[p], b[p]), grid4, n)
+        nodes = np.unique(_cell_nodes(cells, n).reshape(-1))
+        new = nodes[np.isnan(grid[nodes])]
+        for c0 in range(0, len(new), 1 << 18):
+            grid[new[c0:c0 + (1 << 18)]] = sdf_nodes(scene, grid4, n, nodes=new[c0:c0 + (1 << 18)]).astype(np.float32)
+        computed += len(new)
+        t = df_hit(grid.reshape(n, n, n), grid4, r[:, p], a[p], b[p])
+        tend = np.minimum(np.where(np.isfinite(t), t, b[p]), b[p])
+        ri, cells = _segment_cells(o[p], d[p], a[p], tend, grid4, n)
+        bad = np.isnan(grid[_cell_nodes(cells, n)]).any(axis=1)
+        ok = np.ones(len(p), bool)
+        ok[ri[bad]] = False
+        if progress:
+            progress("oracle samples: %d nodes, %d of %d rays pending" % (computed, (~ok).sum(), nr))
+        # a segment sampled to its end covers every cell its walk can visit
+        assert np.all(a[p[~ok]] + reach[p[~ok]] < b[p[~ok]]), "a fully sampled segment read an unsampled cell"
+        reach[p[~ok]] *= 2
+        pending = p[~ok]
+    return grid.reshape(n, n, n), computed

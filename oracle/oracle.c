@@ -132,10 +132,16 @@ static double dist_tri(vec p, const float* verts, const int32_t* t) {
 
 /* Solid test from the object records: each object group is a closed convex
  * polytope with outward faces; the room group (kind 0) faces inwards and
- * everything not strictly inside it is solid. */
+ * everything not strictly inside it is solid.  With `bound` (per group a
+ * sphere holding every vertex, so the whole polytope) an object group whose
+ * sphere does not hold p is skipped: p cannot be inside it. */
 static int is_solid(vec p, const float* verts, const int32_t* tris,
-                    const int32_t* gstart, const int32_t* gcount, const int32_t* gkind, int ngroups) {
+                    const int32_t* gstart, const int32_t* gcount, const int32_t* gkind, int ngroups,
+                    const double* bound) {
     for (int g = 0; g < ngroups; ++g) {
+        if (bound && gkind[g] != 0 &&
+            norm(sub(p, mk(bound[4 * g], bound[4 * g + 1], bound[4 * g + 2]))) > bound[4 * g + 3])
+            continue;
         int inside_all = 1, strictly = 1;
         for (int32_t k = gstart[g]; k < gstart[g] + gcount[g]; ++k) {
             const int32_t* t = tris + 3 * (int64_t)k;
@@ -182,33 +188,54 @@ static void mesh_init(mesh_t* M, const float* verts, const int32_t* tris, int64_
     }
 }
 
+typedef struct {
+    double lb;
+    int g;
+} group_lb;
+
+static int cmp_group_lb(const void* a, const void* b) {
+    double x = ((const group_lb*)a)->lb, y = ((const group_lb*)b)->lb;
+    return (x > y) - (x < y);
+}
+
 /* Signed distance at p: minimum Euclidean distance over every triangle,
- * negative when solid.  With prune != 0 an object group is skipped when its
- * bounding sphere already lies farther than the best distance found so far;
- * this cannot change the minimum (every triangle of that group is at least as
- * far as its bounding sphere). */
+ * negative when solid.  With prune != 0 the group whose bounding sphere is
+ * nearest is measured first, then the groups whose sphere lies within the best
+ * distance so far, in order of that distance, stopping at the first whose
+ * sphere already lies farther than the best distance found;
+ * this cannot change the minimum (every triangle of a group is at least as far
+ * as its bounding sphere, and the minimum of exact values does not depend on
+ * their order).  The solid test skips the groups whose sphere excludes p. */
 static double signed_dist(const mesh_t* M, vec p, int prune) {
     double best = INFINITY;
     if (!prune) {
         for (int64_t t = 0; t < M->ntri; ++t) best = fmin(best, dist_tri(p, M->verts, M->tris + 3 * t));
-    } else {
-        int g0 = 0;
-        double lb0 = INFINITY;
-        for (int g = 0; g < M->ngroups; ++g) {
-            double lb = norm(sub(p, mk(M->bound[4 * g], M->bound[4 * g + 1], M->bound[4 * g + 2]))) - M->bound[4 * g + 3];
-            if (lb < lb0) { lb0 = lb; g0 = g; }
-        }
+        return is_solid(p, M->verts, M->tris, M->gstart, M->gcount, M->gkind, M->ngroups, NULL) ? -best : best;
+    }
+    group_lb* order = (group_lb*)malloc(sizeof(group_lb) * (size_t)(M->ngroups > 0 ? M->ngroups : 1));
+    int g0 = 0;
+    for (int g = 0; g < M->ngroups; ++g) {
+        order[g].lb = norm(sub(p, mk(M->bound[4 * g], M->bound[4 * g + 1], M->bound[4 * g + 2]))) - M->bound[4 * g + 3];
+        order[g].g = g;
+        if (order[g].lb < order[g0].lb) g0 = g;
+    }
+    /* the nearest sphere's group first; then only the groups whose sphere
+     * lies within that distance, nearest first */
+    if (M->ngroups > 0)
         for (int32_t t = M->gstart[g0]; t < M->gstart[g0] + M->gcount[g0]; ++t)
             best = fmin(best, dist_tri(p, M->verts, M->tris + 3 * (int64_t)t));
-        for (int g = 0; g < M->ngroups; ++g) {
-            if (g == g0) continue;
-            double lb = norm(sub(p, mk(M->bound[4 * g], M->bound[4 * g + 1], M->bound[4 * g + 2]))) - M->bound[4 * g + 3];
-            if (lb > best * (1.0 + 1e-12)) continue;
-            for (int32_t t = M->gstart[g]; t < M->gstart[g] + M->gcount[g]; ++t)
-                best = fmin(best, dist_tri(p, M->verts, M->tris + 3 * (int64_t)t));
-        }
+    int nc = 0;
+    for (int g = 0; g < M->ngroups; ++g)
+        if (g != g0 && order[g].lb <= best * (1.0 + 1e-12)) order[nc++] = order[g];
+    qsort(order, (size_t)nc, sizeof(group_lb), cmp_group_lb);
+    for (int q = 0; q < nc; ++q) {
+        if (order[q].lb > best * (1.0 + 1e-12)) break;
+        const int g = order[q].g;
+        for (int32_t t = M->gstart[g]; t < M->gstart[g] + M->gcount[g]; ++t)
+            best = fmin(best, dist_tri(p, M->verts, M->tris + 3 * (int64_t)t));
     }
-    return is_solid(p, M->verts, M->tris, M->gstart, M->gcount, M->gkind, M->ngroups) ? -best : best;
+    free(order);
+    return is_solid(p, M->verts, M->tris, M->gstart, M->gcount, M->gkind, M->ngroups, M->bound) ? -best : best;
 }
 
 /* Exact signed distance at the listed nodes p = lo + (i,j,k) h, node index

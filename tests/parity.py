@@ -98,3 +98,49 @@ def check_shadow(got, ref, margin, orc, verts, tris, rays_soa, segs, label="", m
         msgs.append("excluded fraction %.4f" % excl)
     assert not msgs, label + "\n" + "\n".join(msgs)
     return dict(n=len(t), excluded=float(excl), occluded=int((prim != -1).sum()), df=int((prim == -2).sum()))
+
+
+def split_t1(tau, h, tmax):
+    """The combined query's split point for rays with tmin = 0:
+    t1 = min(fl32(0 + tau h), tmax) (one FP32 rounding, as an FMA gives)."""
+    with np.errstate(over="ignore"):
+        t1 = np.float32(tau) * np.float32(h) if np.isfinite(tau) else np.float32(np.inf)
+    return np.float32(min(t1, np.float32(tmax)))
+
+
+def combined_oracle(orc, verts, tris, grids, g4, rays_soa, tmax, tau):
+    """The oracle's combined query (Eq. 2, first hit, sub-queries in order)
+    for rays with tmin = 0 over several grids of one scene, its triangle
+    sub-query computed once: triangles on [0, t1] (oracle mode 1), then, for
+    the rays they missed, the distance field on [t1, tmax] (mode 2), with the
+    margin composed the way the oracle's combined margin is (the triangle
+    margin alone after a triangle hit, else the smaller of both, and the
+    conditioning of the part that decides).  Returns [(ref, margin, cond)]
+    per grid."""
+    n = np.asarray(rays_soa).shape[1]
+    t1 = split_t1(tau, g4[3], tmax)
+    if t1 > 0:
+        tm = np.full(n, t1, np.float32)
+        tri = orc.query(verts, tris, None, None, rays_soa, tmax, 0.0, mode=orc.MODE_BVH, tmax_ray=tm)
+        mt, ct = orc.margin(verts, tris, None, None, rays_soa, tmax, 0.0, mode=orc.MODE_BVH, tmax_ray=tm)
+        hit = tri[1] >= 0
+    else:
+        tri, hit = None, np.zeros(n, bool)
+    out = []
+    for grid in grids:
+        if t1 < np.float32(tmax) or tau == 0.0:
+            t0 = np.full(n, t1, np.float32)
+            df = orc.query(None, np.zeros((0, 3), np.int32), grid, g4, rays_soa, tmax, 0.0, mode=orc.MODE_DF, tmin=t0)
+            md, cd = orc.margin(None, np.zeros((0, 3), np.int32), grid, g4, rays_soa, tmax, 0.0, mode=orc.MODE_DF,
+                                tmin=t0)
+        else:
+            df = (np.full(n, np.inf), np.full(n, -1, np.int32), np.zeros(n), np.zeros(n))
+            md, cd = np.full(n, np.inf), np.ones(n)
+        if tri is None:
+            out.append((df, md, cd))
+            continue
+        ref = tuple(np.where(hit, a, b) for a, b in zip(tri, df))
+        m = np.where(hit, mt, np.minimum(mt, md))
+        c = np.where(hit, ct, cd)
+        out.append((ref, m, c))
+    return out

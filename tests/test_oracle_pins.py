@@ -816,3 +816,38 @@ def test_combined_margin_composes_the_two_parts(orc):
     mt, _ = tri_margin(orc, v, [[0, 1, 2]], o2, d, 0.0, np.float32(h))
     md, cd = df_margin(orc, grid, g4, o2, d, np.float32(h), 1.0)
     assert m[0] == min(mt[0], md[0]) and c[0] == cd[0] == 1.0
+
+
+def test_composed_combined_query_equals_the_oracles(orc, tiny):
+    """The full-size parity tests compose the combined query from the
+    oracle's triangle and distance-field queries (so the triangle sub-query
+    is computed once for several grids); the composition gives the oracle's
+    own combined results and margins bit for bit at every threshold."""
+    from tests import parity
+    sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    for rays in (tiny["free"], tiny["surf"]):
+        s = rays.soa()
+        for tau in (0.0, 0.5, 1.0, 4.0, 100.0, np.inf):
+            (ref, m, c), = parity.combined_oracle(orc, sc.verts, sc.tris, [grid], g4, s, 2.0, tau)
+            r0 = orc.query(sc.verts, sc.tris, grid, g4, s, 2.0, tau)
+            m0, c0 = orc.margin(sc.verts, sc.tris, grid, g4, s, 2.0, tau)
+            assert all(np.array_equal(a, b) for a, b in zip(ref, r0)), tau
+            assert np.array_equal(m, m0) and np.array_equal(c, c0), tau
+
+
+def test_samples_on_paths_reproduce_the_full_grid(orc, tiny):
+    """The path-sampled grid (exact samples only where each segment's walk
+    reaches before its first root) gives the full grid's first roots and
+    margins bit for bit, and leaves nodes unsampled."""
+    sc, full, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
+    for rays, a in ((tiny["surf"], 0.0), (tiny["free"], 0.1)):
+        s = rays.soa()
+        pg, nn = orc.sdf_grid_on_paths(sc, g4, 32, s, a, 2.0)
+        known = ~np.isnan(pg)
+        assert nn == known.sum() < 32 ** 3
+        assert np.array_equal(pg[known], full[known])
+        assert np.array_equal(orc.df_hit(pg, g4, s, a, 2.0), orc.df_hit(full, g4, s, a, 2.0))
+        tmin = np.full(rays.n, a, np.float32)
+        for x, y in zip(orc.margin(None, np.zeros((0, 3)), pg, g4, s, 2.0, 0.0, mode=orc.MODE_DF, tmin=tmin),
+                        orc.margin(None, np.zeros((0, 3)), full, g4, s, 2.0, 0.0, mode=orc.MODE_DF, tmin=tmin)):
+            assert np.array_equal(x, y)
