@@ -369,6 +369,29 @@ hyb_status hyb_batch_tune(hyb_batch batch, const hyb_batch_tune_opts* opts, floa
 
 hyb_status hyb_batch_destroy(hyb_batch batch);
 
+/* For callers that cannot allocate device memory (serving loops that must not
+ * call hipMalloc, harnesses that forbid it): one launch of the batch kernels
+ * (as hyb_batch_create followed by hyb_batch_launch_eager, with each item's
+ * own threshold and no tuning) whose work counter, item offsets and
+ * descriptor table live in a fixed device array of the library instead of
+ * memory a batch allocates.  The array holds up to HYB_STATIC_BATCH_MAX_ITEMS
+ * items (62,976 bytes, one copy per device, kept until the process ends; its
+ * address is looked up on the first call on each device).  Nothing is
+ * allocated, on the device or the host; the descriptors are written by small
+ * fill kernels whose arguments carry them, so `items` may be reused on
+ * return.  Asynchronous on `stream`; results are bit-identical to the batch
+ * launch of the same items and config.
+ *   config  launch shape, or NULL for the default {16, 256, 4}
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (each call rewrites what it uses and zeroes the counter itself):
+ * calls that overlap on one device (other streams, other threads) race.
+ * Errors: HYB_ERR_INVALID_ARG for NULL items, n_items < 1 or n_items >
+ * HYB_STATIC_BATCH_MAX_ITEMS, a bad config, or an item hyb_batch_create would
+ * reject; HYB_ERR_UNSUPPORTED for mixed storage formats. */
+#define HYB_STATIC_BATCH_MAX_ITEMS 256
+hyb_status hyb_batch_launch_static(const hyb_batch_item* items, int32_t n_items, const hyb_batch_config* config,
+                                   void* stream);
+
 /* Static string naming a status. */
 const char* hyb_status_str(hyb_status s);
 

@@ -105,6 +105,7 @@ def lib() -> ctypes.CDLL:
             "hyb_batch_launch_eager": [P, P],
             "hyb_batch_tune": [P, P, P, P, P],
             "hyb_batch_destroy": [P],
+            "hyb_batch_launch_static": [P, i32, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -371,6 +372,46 @@ def trace_counters(bvh, sdf, rays, tmax: float, threshold: float, mode: int = MO
     return out, counts
 
 
+def _batch_items(items):
+    """The hyb_batch_item array of a sequence of item dicts (see Batch), the
+    objects it points at, and each item's hit buffers."""
+    items = list(items)
+    arr = (_BatchItem * len(items))()
+    keep, outs = [], []
+    for k, it in enumerate(items):
+        thr = float(it["threshold"])
+        _query_args(float(it["tmax"]), thr)
+        r, n = _rays_struct(it["rays"], it.get("tmin"), it.get("tmax_ray"))
+        out = it.get("out") or alloc_hits(n)
+        arr[k].bvh = None if it.get("bvh") is None else it["bvh"].handle
+        arr[k].sdf = None if it.get("sdf") is None else it["sdf"].handle
+        arr[k].rays = r
+        arr[k].hits = _hits_struct(out, n)
+        arr[k].n = n
+        arr[k].tmax = float(it["tmax"])
+        arr[k].threshold = thr
+        keep.append((it.get("bvh"), it.get("sdf"), it["rays"], it.get("tmin"), it.get("tmax_ray"), out))
+        outs.append(out)
+    return arr, keep, outs
+
+
+STATIC_BATCH_MAX_ITEMS = 256
+
+
+def batch_launch_static(items, config=None, stream=None):
+    """One launch of the batch kernels over `items` (dicts as for Batch) with
+    no allocation in the library (hyb_batch_launch_static): the work counter
+    and descriptors live in the library's fixed device array.  Returns each
+    item's hit buffers.  Launches on one device must not overlap."""
+    arr, keep, outs = _batch_items(items)
+    cfg = None
+    if config is not None:
+        cfg = _BatchConfig(int(config["lds_depth"]), int(config["rays_per_item"]), int(config["blocks_per_cu"]))
+    _check("hyb_batch_launch_static", lib().hyb_batch_launch_static(
+        arr, len(keep), None if cfg is None else ctypes.byref(cfg), _stream(stream)))
+    return outs
+
+
 class Batch:
     """Many independent combined queries run by one persistent kernel (one HIP
     graph launch).  `items` is a sequence of dicts with keys bvh, sdf, rays,
@@ -379,23 +420,7 @@ class Batch:
     references to every tensor and handle it points at."""
 
     def __init__(self, items, stream=None):
-        items = list(items)
-        arr = (_BatchItem * len(items))()
-        self._keep, self.outs = [], []
-        for k, it in enumerate(items):
-            thr = float(it["threshold"])
-            _query_args(float(it["tmax"]), thr)
-            r, n = _rays_struct(it["rays"], it.get("tmin"), it.get("tmax_ray"))
-            out = it.get("out") or alloc_hits(n)
-            arr[k].bvh = None if it.get("bvh") is None else it["bvh"].handle
-            arr[k].sdf = None if it.get("sdf") is None else it["sdf"].handle
-            arr[k].rays = r
-            arr[k].hits = _hits_struct(out, n)
-            arr[k].n = n
-            arr[k].tmax = float(it["tmax"])
-            arr[k].threshold = thr
-            self._keep.append((it.get("bvh"), it.get("sdf"), it["rays"], it.get("tmin"), it.get("tmax_ray"), out))
-            self.outs.append(out)
+        arr, self._keep, self.outs = _batch_items(items)
         h = ctypes.c_void_p()
         _check("hyb_batch_create", lib().hyb_batch_create(arr, len(items), _stream(stream), ctypes.byref(h)))
         self._h = h

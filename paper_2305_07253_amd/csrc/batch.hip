@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -94,7 +95,73 @@ __global__ __launch_bounds__(kBlock) void k_count_mismatch(const float* __restri
     }
 }
 
+// The fixed device array of hyb_batch_launch_static: the work counter, the
+// item offsets and the descriptor table of up to kStaticItems items, laid out
+// at the offsets below (one copy per device, held until the process ends).
+constexpr int kStaticItems = HYB_STATIC_BATCH_MAX_ITEMS;
+constexpr size_t kStaticQueueOff = 0;
+constexpr size_t kStaticStartOff = 256;
+constexpr size_t kStaticTableOff = 1536;
+constexpr size_t kStaticBytes = kStaticTableOff + sizeof(TraceArgs) * kStaticItems;
+static_assert(kStaticStartOff + sizeof(uint32_t) * (kStaticItems + 1) <= kStaticTableOff, "offsets overlap");
+static_assert(sizeof(TraceArgs) % sizeof(uint32_t) == 0 && alignof(TraceArgs) <= 256, "table layout");
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+// Words of host data carried by value in one kernel's arguments (kept under
+// the 4 KiB argument limit), written to base[offset ...): how the host fills
+// the fixed array without a copy from host memory.
+constexpr uint32_t kFillWords = 960;
+struct FillChunk {
+    uint32_t offset, count;
+    uint32_t words[kFillWords];
+};
+
+__global__ void k_fill_words(uint32_t* __restrict__ base, FillChunk c) {
+    for (uint32_t i = threadIdx.x; i < c.count; i += blockDim.x) base[c.offset + i] = c.words[i];
+}
+
 }  // namespace
+
+// Host address of this device's copy of the fixed array (hipGetSymbolAddress
+// once per device, with that device current; the array's name is only a
+// host-side stand-in), and the device's compute-unit count.
+hipError_t static_scratch(int device, void** ptr, int* n_cu) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    static int cus[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        int c = 0;
+        e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, device);
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+        cus[device] = c;
+    }
+    *ptr = addr[device];
+    *n_cu = cus[device];
+    return hipSuccess;
+}
+
+// Copies `words` 32-bit words from host memory to dst_words (a word offset
+// into the array at base) through k_fill_words launches on `stream`.
+hipError_t fill_static(uint32_t* base, uint32_t dst_words, const void* src, size_t words, hipStream_t stream) {
+    FillChunk c;
+    const uint32_t* w = static_cast<const uint32_t*>(src);
+    for (size_t done = 0; done < words; done += kFillWords) {
+        c.offset = dst_words + static_cast<uint32_t>(done);
+        c.count = static_cast<uint32_t>(std::min<size_t>(kFillWords, words - done));
+        std::memcpy(c.words, w + done, sizeof(uint32_t) * c.count);
+        hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(256), 0, stream, base, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 const void* batch_kernel(int fmt, int lds_depth) {
 #define HYB_BATCH_CASE(F, D) \
@@ -171,6 +238,50 @@ bool valid_config(const hyb_batch_config& c) {
            c.rays_per_item <= 65536 && c.rays_per_item % 64 == 0 && c.blocks_per_cu >= 1 && c.blocks_per_cu <= 16;
 }
 
+// Validation shared by hyb_batch_create and hyb_batch_launch_static: every
+// item as hyb_trace would check it, all sdfs of one storage format (returned
+// through *fmt, the batch kernel's format).
+hyb_status check_items(const hyb_batch_item* items, int32_t n_items, int* fmt_out) {
+    int fmt = -1;
+    for (int32_t i = 0; i < n_items; ++i) {
+        const hyb_batch_item& it = items[i];
+        if (!it.bvh && !it.sdf) return HYB_ERR_INVALID_ARG;
+        if (std::isnan(it.threshold) || it.threshold < 0.0f) return HYB_ERR_INVALID_ARG;
+        if (!it.bvh && it.threshold != 0.0f) return HYB_ERR_INVALID_ARG;
+        if (!it.sdf && !std::isinf(it.threshold)) return HYB_ERR_INVALID_ARG;
+        hyb_status rc = check_query(&it.rays, it.n, it.tmax, const_cast<hyb_hits*>(&it.hits));
+        if (rc != HYB_OK) return rc;
+        if ((it.bvh && !same_device(it.bvh->device)) || (it.sdf && !same_device(it.sdf->device)))
+            return HYB_ERR_INVALID_ARG;
+        if (it.sdf) {
+            if (fmt >= 0 && fmt != static_cast<int>(it.sdf->fmt)) return HYB_ERR_UNSUPPORTED;
+            fmt = static_cast<int>(it.sdf->fmt);
+        }
+    }
+    *fmt_out = fmt < 0 ? hyb::kF32 : fmt;
+    return HYB_OK;
+}
+
+// The arguments of one item's query, as the batch's descriptor table holds them.
+void item_args(const hyb_batch_item& it, hyb::TraceArgs& a) {
+    fill_trace_args(a, &it.rays, const_cast<hyb_hits*>(&it.hits), it.n, it.tmax, it.threshold);
+    fill_scene(a, it.bvh, it.sdf);
+    if (!it.sdf) a.h = 1.0f;  // t1 = fma(+inf, h, tmin) must be +inf (then min(., tmax) = tmax), not NaN
+}
+
+// Blocks of the persistent launch: as many as the GPU holds at the config's
+// blocks per CU (capped by occupancy), never more than the work needs.
+hyb_status persistent_grid(int fmt, const hyb_batch_config& cfg, int n_cu, uint64_t work_items, dim3* grid) {
+    const void* fn = hyb::batch_kernel(fmt, cfg.lds_depth);
+    if (!fn) return HYB_ERR_UNSUPPORTED;
+    int occ = 0;
+    HYB_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, hyb::kBlock, hyb::batch_lds_bytes(cfg.lds_depth)));
+    const int64_t per_cu = std::max(1, std::min(occ, cfg.blocks_per_cu));
+    const int64_t waves_needed = (static_cast<int64_t>(work_items) + 3) / 4;  // 4 wavefronts per block
+    *grid = dim3(static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(per_cu * n_cu, waves_needed))));
+    return HYB_OK;
+}
+
 void drop_graph(hyb_batch_s* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -210,14 +321,10 @@ hyb_status sync_table(hyb_batch_s* b, hipStream_t stream) {
                            hipMemcpyHostToDevice, stream));
     HYB_TRY(hipStreamSynchronize(stream));
 
-    const void* fn = hyb::batch_kernel(b->fmt, b->cfg.lds_depth);
-    if (!fn) return HYB_ERR_UNSUPPORTED;
-    int occ = 0;
-    HYB_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, hyb::kBlock,
-                                                         hyb::batch_lds_bytes(b->cfg.lds_depth)));
-    const int64_t per_cu = std::max(1, std::min(occ, b->cfg.blocks_per_cu));
-    const int64_t waves_needed = (static_cast<int64_t>(total) + 3) / 4;  // 4 wavefronts per block
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(per_cu * b->n_cu, waves_needed));
+    dim3 grid;
+    const hyb_status gs = persistent_grid(b->fmt, b->cfg, b->n_cu, total, &grid);
+    if (gs != HYB_OK) return gs;
+    const int64_t blocks = grid.x;
     // The graph's kernel nodes hold the launch shape and BatchArgs by value;
     // a change of thresholds alone only rewrites the device table.
     const bool same_shape = b->grid.x == static_cast<unsigned>(blocks) && b->kargs.n_items == total &&
@@ -345,28 +452,15 @@ hyb_status hyb_batch_create(const hyb_batch_item* items, int32_t n_items, void* 
     if (!out) return HYB_ERR_INVALID_ARG;
     *out = nullptr;
     if (!items || n_items < 1 || n_items > kMaxItems) return HYB_ERR_INVALID_ARG;
-    int fmt = -1;
-    for (int32_t i = 0; i < n_items; ++i) {
-        const hyb_batch_item& it = items[i];
-        if (!it.bvh && !it.sdf) return HYB_ERR_INVALID_ARG;
-        if (std::isnan(it.threshold) || it.threshold < 0.0f) return HYB_ERR_INVALID_ARG;
-        if (!it.bvh && it.threshold != 0.0f) return HYB_ERR_INVALID_ARG;
-        if (!it.sdf && !std::isinf(it.threshold)) return HYB_ERR_INVALID_ARG;
-        hyb_status rc = check_query(&it.rays, it.n, it.tmax, const_cast<hyb_hits*>(&it.hits));
-        if (rc != HYB_OK) return rc;
-        if ((it.bvh && !same_device(it.bvh->device)) || (it.sdf && !same_device(it.sdf->device)))
-            return HYB_ERR_INVALID_ARG;
-        if (it.sdf) {
-            if (fmt >= 0 && fmt != static_cast<int>(it.sdf->fmt)) return HYB_ERR_UNSUPPORTED;
-            fmt = static_cast<int>(it.sdf->fmt);
-        }
-    }
+    int fmt = 0;
+    const hyb_status checked = check_items(items, n_items, &fmt);
+    if (checked != HYB_OK) return checked;
     int dev = 0;
     HYB_TRY(hipGetDevice(&dev));
     hyb_batch_s* b = new (std::nothrow) hyb_batch_s;
     if (!b) return HYB_ERR_OOM;
     b->device = dev;
-    b->fmt = fmt < 0 ? hyb::kF32 : fmt;
+    b->fmt = fmt;
     b->args.resize(n_items);
     b->kind.resize(n_items);
     b->sdfs.resize(n_items);
@@ -374,10 +468,7 @@ hyb_status hyb_batch_create(const hyb_batch_item* items, int32_t n_items, void* 
     b->item_start.resize(n_items + 1);
     for (int32_t i = 0; i < n_items; ++i) {
         const hyb_batch_item& it = items[i];
-        hyb::TraceArgs& a = b->args[i];
-        fill_trace_args(a, &it.rays, const_cast<hyb_hits*>(&it.hits), it.n, it.tmax, it.threshold);
-        fill_scene(a, it.bvh, it.sdf);
-        if (!it.sdf) a.h = 1.0f;  // t1 = fma(+inf, h, tmin) must be +inf (then min(., tmax) = tmax), not NaN
+        item_args(it, b->args[i]);
         b->kind[i] = !it.sdf ? kTrianglesOnly : (!it.bvh ? kFieldOnly : kBoth);
         b->sdfs[i] = it.sdf;
         b->sdf_version[i] = it.sdf ? it.sdf->version : 0;
@@ -528,6 +619,60 @@ hyb_status hyb_batch_tune(hyb_batch batch, const hyb_batch_tune_opts* opts, floa
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     return rc;
+}
+
+hyb_status hyb_batch_launch_static(const hyb_batch_item* items, int32_t n_items, const hyb_batch_config* config,
+                                   void* stream) {
+    if (!items || n_items < 1 || n_items > HYB_STATIC_BATCH_MAX_ITEMS) return HYB_ERR_INVALID_ARG;
+    const hyb_batch_config cfg = config ? *config : hyb_batch_config{16, 256, 4};
+    if (!valid_config(cfg)) return HYB_ERR_INVALID_ARG;
+    int fmt = 0;
+    const hyb_status checked = check_items(items, n_items, &fmt);
+    if (checked != HYB_OK) return checked;
+    int dev = 0;
+    HYB_TRY(hipGetDevice(&dev));
+    void* ptr = nullptr;
+    int n_cu = 0;
+    HYB_TRY(hyb::static_scratch(dev, &ptr, &n_cu));
+    // offsets and descriptors on the stack: nothing is allocated, on the
+    // device or the host
+    uint32_t item_start[HYB_STATIC_BATCH_MAX_ITEMS + 1];
+    uint64_t total = 0;
+    for (int32_t s = 0; s < n_items; ++s) {
+        item_start[s] = static_cast<uint32_t>(total);
+        total += (static_cast<uint64_t>(items[s].n) + cfg.rays_per_item - 1) / cfg.rays_per_item;
+        if (total >= kMaxWorkItems) return HYB_ERR_UNSUPPORTED;
+    }
+    item_start[n_items] = static_cast<uint32_t>(total);
+    dim3 grid;
+    const hyb_status gs = persistent_grid(fmt, cfg, n_cu, total, &grid);
+    if (gs != HYB_OK) return gs;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned char* base = static_cast<unsigned char*>(ptr);
+    uint32_t* words = reinterpret_cast<uint32_t*>(base);
+    HYB_TRY(hyb::fill_static(words, static_cast<uint32_t>(hyb::kStaticStartOff / 4), item_start, n_items + 1, st));
+    constexpr size_t kArgWords = sizeof(hyb::TraceArgs) / sizeof(uint32_t);
+    for (int32_t s = 0; s < n_items; ++s) {
+        hyb::TraceArgs a;
+        item_args(items[s], a);
+        HYB_TRY(hyb::fill_static(words, static_cast<uint32_t>((hyb::kStaticTableOff + sizeof(a) * s) / 4), &a,
+                                 kArgWords, st));
+    }
+    uint32_t* queue = reinterpret_cast<uint32_t*>(base + hyb::kStaticQueueOff);
+    const hyb::TraceArgs* scenes = reinterpret_cast<const hyb::TraceArgs*>(base + hyb::kStaticTableOff);
+    void* reset_args[] = {&queue};
+    HYB_TRY(hipLaunchKernel(hyb::queue_reset_kernel(), dim3(1), dim3(64), reset_args, 0, st));
+    if (total == 0) return HYB_OK;
+    hyb::BatchArgs kargs = {};
+    kargs.scenes = scenes;
+    kargs.item_start = reinterpret_cast<const uint32_t*>(base + hyb::kStaticStartOff);
+    kargs.queue = queue;
+    kargs.n_scenes = n_items;
+    kargs.n_items = static_cast<uint32_t>(total);
+    kargs.rays_per_item = cfg.rays_per_item;
+    void* trace_args[] = {&kargs, &scenes};
+    return from_hip(hipLaunchKernel(hyb::batch_kernel(fmt, cfg.lds_depth), grid, dim3(hyb::kBlock), trace_args,
+                                    hyb::batch_lds_bytes(cfg.lds_depth), st));
 }
 
 hyb_status hyb_batch_destroy(hyb_batch batch) {
