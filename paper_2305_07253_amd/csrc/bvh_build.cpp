@@ -215,12 +215,16 @@ void build_entries(BvhHost* out) {
     int levels = 0;
     size_t total = 0;
     for (int e = E; e >= 1; e >>= 1) {
-        total += static_cast<size_t>(e) * e * e;
+        const size_t w = static_cast<size_t>(2 * e - 1);
+        total += w * w * w;
         ++levels;
     }
     out->entry.assign(total, kEmptyRef);
-    // every leaf joins the entry of each finest voxel its box overlaps, the
-    // box grown by a margin (FP32 rounding of segment end points is far below it)
+    // every leaf joins each finest half-cell its box overlaps, the box grown
+    // by a margin (FP32 rounding of segment end points is far below it)
+    int H = 2 * E;
+    const double half = 0.5 * static_cast<double>(size);
+    std::vector<int32_t> cells(static_cast<size_t>(H) * H * H, kEmptyRef);
     const double margin = 1e-3 * size;
     for (size_t i = 0; i < n4; ++i)
         for (int c = 0; c < 4; ++c) {
@@ -231,32 +235,48 @@ void build_entries(BvhHost* out) {
             for (int a = 0; a < 3; ++a) {
                 const double qlo = q[8 * a + c], qhi = q[8 * a + 4 + c];
                 const double slack = margin + 1e-6 * (1.0 + std::max(std::fabs(qlo), std::fabs(qhi)));
-                const double u0 = (qlo - slack - out->entry_lo[a]) / size, u1 = (qhi + slack - out->entry_lo[a]) / size;
-                v0[a] = static_cast<int>(std::floor(std::min(std::max(u0, 0.0), E - 1.0)));
-                v1[a] = static_cast<int>(std::floor(std::min(std::max(u1, 0.0), E - 1.0)));
+                const double u0 = (qlo - slack - out->entry_lo[a]) / half, u1 = (qhi + slack - out->entry_lo[a]) / half;
+                v0[a] = static_cast<int>(std::floor(std::min(std::max(u0, 0.0), H - 1.0)));
+                v1[a] = static_cast<int>(std::floor(std::min(std::max(u1, 0.0), H - 1.0)));
             }
             for (int z = v0[2]; z <= v1[2]; ++z)
                 for (int y = v0[1]; y <= v1[1]; ++y)
                     for (int x = v0[0]; x <= v1[0]; ++x) {
-                        int32_t& slot = out->entry[x + static_cast<size_t>(E) * (y + static_cast<size_t>(E) * z)];
+                        int32_t& slot = cells[x + static_cast<size_t>(H) * (y + static_cast<size_t>(H) * z)];
                         slot = lca(slot, r);
                     }
         }
     size_t off = 0;
-    for (int e = E; e > 1; e >>= 1) {
-        const size_t next = off + static_cast<size_t>(e) * e * e;
-        const int h = e / 2;
+    for (int l = 0; l < levels; ++l) {
+        // windows of 2 x 2 x 2 half-cells of this level
+        const int W = H - 1;
+        for (int z = 0; z < W; ++z)
+            for (int y = 0; y < W; ++y)
+                for (int x = 0; x < W; ++x) {
+                    int32_t acc = kEmptyRef;
+                    for (int c = 0; c < 8; ++c) {
+                        const int cx = x + (c & 1), cy = y + ((c >> 1) & 1), cz = z + (c >> 2);
+                        acc = lca(acc, cells[cx + static_cast<size_t>(H) * (cy + static_cast<size_t>(H) * cz)]);
+                    }
+                    out->entry[off + x + static_cast<size_t>(W) * (y + static_cast<size_t>(W) * z)] = acc;
+                }
+        off += static_cast<size_t>(W) * W * W;
+        if (l + 1 == levels) break;
+        // the next level's half-cells: 2 x 2 x 2 of this level's
+        const int h = H / 2;
+        std::vector<int32_t> up(static_cast<size_t>(h) * h * h, kEmptyRef);
         for (int z = 0; z < h; ++z)
             for (int y = 0; y < h; ++y)
                 for (int x = 0; x < h; ++x) {
                     int32_t acc = kEmptyRef;
                     for (int c = 0; c < 8; ++c) {
                         const int cx = 2 * x + (c & 1), cy = 2 * y + ((c >> 1) & 1), cz = 2 * z + (c >> 2);
-                        acc = lca(acc, out->entry[off + cx + static_cast<size_t>(e) * (cy + static_cast<size_t>(e) * cz)]);
+                        acc = lca(acc, cells[cx + static_cast<size_t>(H) * (cy + static_cast<size_t>(H) * cz)]);
                     }
-                    out->entry[next + x + static_cast<size_t>(h) * (y + static_cast<size_t>(h) * z)] = acc;
+                    up[x + static_cast<size_t>(h) * (y + static_cast<size_t>(h) * z)] = acc;
                 }
-        off = next;
+        cells.swap(up);
+        H = h;
     }
     out->entry_res = E;
     out->entry_levels = levels;

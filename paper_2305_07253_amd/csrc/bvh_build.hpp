@@ -32,13 +32,17 @@ struct BvhHost {
     std::vector<float> nodes4;
     int32_t depth4 = 0;
     int32_t stack4 = 0;  // most stack entries a nodes4 traversal can hold
-    // Traversal entry points: levels l = 0 .. entry_levels-1 of cubic voxel
-    // grids with entry_res >> l voxels per side over the mesh bounds (voxel
-    // side entry_size << l, origin entry_lo), concatenated finest first, x
-    // fastest.  Each voxel holds the lowest common ancestor (a nodes4 index,
-    // or a leaf reference) of every leaf whose box overlaps the voxel grown by
-    // a small margin, or kEmptyRef when none does.  A segment inside one voxel
-    // can only hit triangles under that voxel's entry.  entry_res == 0: none.
+    // Traversal entry points: levels l = 0 .. entry_levels-1.  Level l cuts
+    // the cube of entry_res voxels of side entry_size (origin entry_lo) into
+    // 2 (entry_res >> l) half-cells of side entry_size << l / 2 per axis and
+    // stores one entry per window of 2 x 2 x 2 neighbouring half-cells,
+    // (2 (entry_res >> l) - 1)^3 windows, x fastest, levels concatenated
+    // finest first.  A window's entry is the lowest common ancestor (a nodes4
+    // index, or a leaf reference) of every leaf whose box overlaps the window
+    // grown by a small margin, or kEmptyRef when none does.  A segment inside
+    // one window can only hit triangles under its entry; any segment less
+    // than half a cell long per axis lies in some window of that level (the
+    // windows overlap by half their side).  entry_res == 0: none.
     std::vector<int32_t> entry;
     int32_t entry_res = 0, entry_levels = 0;
     float entry_lo[3] = {0, 0, 0}, entry_size = 0.0f;

@@ -166,15 +166,20 @@ HYB_HD void order2(float& ka, int& ra, float& kb, int& rb) {
 // Closest triangle hit on [seg_lo, seg_hi] (both inclusive) through the
 // four-wide BVH (nodes4 layout, 128-byte nodes).  Equal t goes to the smallest
 // original triangle id, independent of traversal order.  With ANY the
-// traversal stops at the first intersection it finds (any-hit).  The children
-// a node's ray hits are visited nearest first: the nearest is entered, the
-// others are pushed farthest first.  `stack` points at this lane's first LDS
-// slot; consecutive entries are `stride` ints apart (one slot per thread of
-// the block, no bank conflicts); entries beyond LDS go to a private spill area.
+// traversal stops at the first intersection it finds (any-hit).  With `sort`
+// the children a node's ray hits are visited nearest first (the nearest is
+// entered, the others are pushed farthest first), which lets a closest hit
+// prune farther boxes early on long segments; without it they go in slot
+// order, which costs fewer instructions and gives the same hit (the order
+// only changes which boxes a closer hit prunes, never the result).  `stack`
+// points at this lane's first LDS slot; consecutive entries are `stride` ints
+// apart (one slot per thread of the block, no bank conflicts); entries beyond
+// LDS go to a private spill area.
 template <bool COUNT, bool ANY = false, int LDS = kLdsDepth>
 HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                        float ox, float oy, float oz, float dx, float dy, float dz,
-                       float seg_lo, float seg_hi, int* stack, int stride, Counters& cnt, int start = 0) {
+                       float seg_lo, float seg_hi, int* stack, int stride, Counters& cnt, int start = 0,
+                       bool sort = true) {
     Hit best;
     best.t = seg_hi;
     best.prim = -1;
@@ -203,23 +208,45 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
             box_clip(br, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, seg_lo, hi, tn, tf);
             float k3 = tn <= tf ? tn : kNone;
             int r0 = bits_i(rf.x), r1 = bits_i(rf.y), r2 = bits_i(rf.z), r3 = bits_i(rf.w);
-            // sorting network, nearest first; misses (+inf) sink to the end
-            order2(k0, r0, k1, r1);
-            order2(k2, r2, k3, r3);
-            order2(k0, r0, k2, r2);
-            order2(k1, r1, k3, r3);
-            order2(k1, r1, k2, r2);
-            if (k0 < kNone) {
-                const int push[3] = {r3, r2, r1};
-                const bool take[3] = {k3 < kNone, k2 < kNone, k1 < kNone};
-                for (int c = 0; c < 3; ++c) {
-                    if (!take[c]) continue;
-                    if (sp < LDS) stack[sp * stride] = push[c];
-                    else spill[sp - LDS] = push[c];
-                    ++sp;
+            if (sort) {
+                // sorting network, nearest first; misses (+inf) sink to the end
+                order2(k0, r0, k1, r1);
+                order2(k2, r2, k3, r3);
+                order2(k0, r0, k2, r2);
+                order2(k1, r1, k3, r3);
+                order2(k1, r1, k2, r2);
+                if (k0 < kNone) {
+                    const int push[3] = {r3, r2, r1};
+                    const bool take[3] = {k3 < kNone, k2 < kNone, k1 < kNone};
+                    for (int c = 0; c < 3; ++c) {
+                        if (!take[c]) continue;
+                        if (sp < LDS) stack[sp * stride] = push[c];
+                        else spill[sp - LDS] = push[c];
+                        ++sp;
+                    }
+                    ref = r0;
+                    continue;
                 }
-                ref = r0;
-                continue;
+            } else {
+                // slot order: enter the first child hit, push the others
+                const int rr[4] = {r3, r2, r1, r0};
+                const bool hh[4] = {k3 < kNone, k2 < kNone, k1 < kNone, k0 < kNone};
+                int next = 0;
+                bool have = false;
+                for (int c = 0; c < 4; ++c) {
+                    if (!hh[c]) continue;
+                    if (have) {
+                        if (sp < LDS) stack[sp * stride] = next;
+                        else spill[sp - LDS] = next;
+                        ++sp;
+                    }
+                    next = rr[c];
+                    have = true;
+                }
+                if (have) {
+                    ref = next;
+                    continue;
+                }
             }
         } else {
             const int info = ~ref;
@@ -634,12 +661,19 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
         return kDfContinue;
     }
     if (val <= 0.0f) return kDfHit;
+    // span of the ray inside the current cell, from the in-cell fractions
+    const float ex = fmaf(fx, r.mx, r.ex);
+    const float ey = fmaf(fy, r.my, r.ey);
+    const float ez = fmaf(fz, r.mz, r.ez);
+    const float exit_span = fmaxf(fminf(fminf(ex, ey), ez), 0.0f);
     // A sphere step far from the surface, unless it would be shorter than half
-    // a cell: on a grid whose bound L is inflated (one extreme sample anywhere
-    // makes every step short) the exact cell step is longer.  For any grid
-    // with L < 2, g > h already gives safe > h / 2, so this only changes
-    // the march on such grids.
-    if (val > g.h && safe >= 0.5f * g.h && !r.walk_only) {
+    // a cell (on a grid whose bound L is inflated, one extreme sample anywhere
+    // makes every step short, and the exact cell step is longer; for any grid
+    // with L < 2, g > h already gives safe > h / 2); and near the surface
+    // whenever the certified distance already passes the cell's exit, which
+    // covers the cell step's span and more.  Either kind moves the ray at
+    // least half a cell or into the next cell.
+    if (((val > g.h && safe >= 0.5f * g.h) || safe > exit_span) && !r.walk_only) {
         r.walk = false;
         r.cover = r.t + safe;
         r.t += r.relax ? kOverRelax * safe : safe;
@@ -651,11 +685,7 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
         return kDfContinue;
     }
     r.walk = true;
-    // span of the ray inside the current cell, from the in-cell fractions
-    const float ex = fmaf(fx, r.mx, r.ex);
-    const float ey = fmaf(fy, r.my, r.ey);
-    const float ez = fmaf(fz, r.mz, r.ez);
-    const float t_exit = r.t + fmaxf(fminf(fminf(ex, ey), ez), 0.0f);
+    const float t_exit = r.t + exit_span;
     const int axis = (ex <= ey && ex <= ez) ? 0 : (ey <= ez ? 1 : 2);
     if (min_bits(f) <= 0) {
         // some corner at or below zero: the cell's cubic along the ray
@@ -826,38 +856,46 @@ inline float certified_slack(float h, int n) {
 }
 
 // Where a traversal of the segment [t0, t1] may start: the entry of the
-// finest voxel of the pyramid that holds the whole segment, grown by a margin
-// over the FP32 rounding of its end points (every triangle the segment can hit
-// overlaps that voxel, so it lies under the voxel's entry), else the root.
-// Parts of the segment outside the pyramid's box reach no triangle, so the end
-// points are clamped into it.
+// finest window of the pyramid (2 x 2 x 2 half-cells, windows overlapping by
+// a half-cell) that holds the whole segment, grown by a margin over the FP32
+// rounding of its end points (every triangle the segment can hit overlaps
+// that window, so it lies under the window's entry), else the root.  Parts of
+// the segment outside the pyramid's box reach no triangle, so the end points
+// are clamped into it.
 HYB_HD int entry_node(const TraceArgs& a, float ox, float oy, float oz, float dx, float dy, float dz, float t0,
                       float t1) {
-    // a segment longer than 8 finest voxels almost never fits one voxel deep
+    // a segment longer than 8 finest voxels almost never fits one window deep
     // enough to skip levels: start at the root without looking
     if (a.entry_res == 0 || !((t1 - t0) * a.entry_inv <= 8.0f)) return 0;
-    const int E = a.entry_res;
+    const int H = 2 * a.entry_res;  // finest half-cells per axis
     int ia[3], ib[3];
     const float o[3] = {ox, oy, oz}, d[3] = {dx, dy, dz}, lo[3] = {a.entry_lo_x, a.entry_lo_y, a.entry_lo_z};
+    const float inv_half = 2.0f * a.entry_inv;
     for (int k = 0; k < 3; ++k) {
         const float p0 = fmaf(t0, d[k], o[k]), p1 = fmaf(t1, d[k], o[k]);
         const float m = 1e-6f * (1.0f + fmaxf(fabsf(p0), fabsf(p1)));
-        const float u0 = (fminf(p0, p1) - m - lo[k]) * a.entry_inv;
-        const float u1 = (fmaxf(p0, p1) + m - lo[k]) * a.entry_inv;
-        ia[k] = (int)floorf(fminf(fmaxf(u0, 0.0f), (float)(E - 1)));
-        ib[k] = (int)floorf(fminf(fmaxf(u1, 0.0f), (float)(E - 1)));
+        const float u0 = (fminf(p0, p1) - m - lo[k]) * inv_half;
+        const float u1 = (fmaxf(p0, p1) + m - lo[k]) * inv_half;
+        ia[k] = (int)floorf(fminf(fmaxf(u0, 0.0f), (float)(H - 1)));
+        ib[k] = (int)floorf(fminf(fmaxf(u1, 0.0f), (float)(H - 1)));
     }
     int level = 0, off = 0;
     for (; level + 1 < a.entry_levels; ++level) {
-        if ((ia[0] >> level) == (ib[0] >> level) && (ia[1] >> level) == (ib[1] >> level) &&
-            (ia[2] >> level) == (ib[2] >> level))
+        if ((ib[0] >> level) - (ia[0] >> level) <= 1 && (ib[1] >> level) - (ia[1] >> level) <= 1 &&
+            (ib[2] >> level) - (ia[2] >> level) <= 1)
             break;
-        const int e = E >> level;
-        off += e * e * e;
+        const int w = (H >> level) - 1;
+        off += w * w * w;
     }
-    const int e = E >> level;
-    return a.entry[off + (ia[0] >> level) + e * ((ia[1] >> level) + e * (ia[2] >> level))];
+    const int w = (H >> level) - 1;
+    const int x = min(ia[0] >> level, w - 1), y = min(ia[1] >> level, w - 1), z = min(ia[2] >> level, w - 1);
+    return a.entry[off + x + w * (y + w * z)];
 }
+
+// Triangle segments at most this many voxels long are traversed without
+// ordering the children (their boxes mostly all overlap the short segment, so
+// nearest-first order prunes little and costs a sorting network per node).
+constexpr float kShortSegment = 4.0f;
 
 // One ray of a query (the body of the trace kernels).
 template <int MODE, int FMT, bool COUNT, int LDS = kLdsDepth>
@@ -890,6 +928,7 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
             // runs first (Section 2, out-of-order any-hit processing).
             const float t1 = fminf(fmaf(a.tau, a.h, tmin), tmax);
             const float t2 = fmaxf(fmaf(-a.tau_end, a.h, tmax), t1);
+            const bool sort = !(a.tau <= kShortSegment && a.tau_end <= kShortSegment);
             if (t2 > t1 || (a.tau == 0.0f && a.tau_end == 0.0f)) {
                 const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, t2, cnt);
                 if (t != __builtin_inff()) {  // NaN: see df_first_root
@@ -899,10 +938,10 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
             }
             if (hit.prim == -1 && t1 > tmin)
                 hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt,
-                                                    entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1));
+                                                    entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1), sort);
             if (hit.prim == -1 && tmax > t2)
                 hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, t2, tmax, stack, stride, cnt,
-                                                    entry_node(a, ox, oy, oz, dx, dy, dz, t2, tmax));
+                                                    entry_node(a, ox, oy, oz, dx, dy, dz, t2, tmax), sort);
         } else {
             // Eq. (2) with two sub-queries processed in order (first hit):
             // triangles on [tmin, t1]; the distance field on [t1, tmax] only
@@ -910,7 +949,8 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
             const float t1 = fminf(fmaf(a.tau, a.h, tmin), tmax);
             if (t1 > tmin)
                 hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride,
-                                                     cnt, entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1));
+                                                     cnt, entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1),
+                                                     !(a.tau <= kShortSegment));
             if (hit.prim < 0 && (t1 < tmax || a.tau == 0.0f)) {
                 const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, tmax, cnt);
                 if (t != __builtin_inff()) {  // NaN: see df_first_root

@@ -10,8 +10,12 @@
 
 namespace hyb {
 
+// One-cell F16 bricks: the compiler's 74 VGPRs allow six wavefronts per
+// SIMD; held to 72 they fit seven.
 template <int MODE, int FMT, bool COUNT>
-__global__ __launch_bounds__(kBlock) void k_trace(TraceArgs a) {
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(FMT == kF16 && !COUNT && (MODE == kCombined || MODE == kDfOnly) ? 7 : 1)))
+void k_trace(TraceArgs a) {
     extern __shared__ int s_stack[];
     const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x, kXcdRun) * kBlock + threadIdx.x;
     if (i >= a.n) return;
