@@ -762,13 +762,16 @@ def bench_batch(args, torch, hyb, W, dev, stream):
     log("graph %.3f ms, eager %.3f ms, %d per-scene launches %.3f ms (captured: %s ms)" % (
         ms_graph, ms_eager, len(items), ms_loop, ms_loop_graph))
 
-    # algorithmic bytes at the tuned thresholds (same accounting as the GI line)
-    total_bytes = 0.0
+    # algorithmic bytes and lane operations at the tuned thresholds (same
+    # accounting as the GI line)
+    total_bytes, total_ops = 0.0, 0.0
     for k, it in enumerate(items):
         _, cnt = hyb.trace_counters(it["bvh"], it["sdf"], it["rays"], TMAX, taus[k], hyb.MODE_COMBINED)
         c = cnt.double().sum(dim=0).cpu().numpy()
-        total_bytes += 40.0 * meta[k]["rays"] + 128 * c[0] + 48 * c[1] + 32 * c[2]
+        total_bytes += BYTES_RAY * meta[k]["rays"] + BYTES_NODE * c[0] + BYTES_TRI * c[1] + BYTES_FETCH * c[2]
+        total_ops += OPS_NODE * c[0] + OPS_TRI * c[1] + OPS_FETCH * c[2]
     achieved = total_bytes / (ms_graph * 1e-3) / 1e9
+    alu = total_ops / (ms_graph * 1e-3) / 1e12
     hist = {}
     for t in taus:
         key = "inf" if math.isinf(t) else t
@@ -785,8 +788,11 @@ def bench_batch(args, torch, hyb, W, dev, stream):
         "ms_default_config_tau1": ms_default, "default_config": default_cfg,
         "tuned_config": cfg, "tune_seconds": tune_s, "max_error_rate": args.max_error,
         "threshold_histogram": hist, "error_rate_max": float(np.max(err)), "error_rate_mean": float(np.mean(err)),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "bytes_per_ray": total_bytes / n_rays},
+        "roofline": {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (VALU lane operations)",
+                     "frac": alu / VALU_PEAK_TOPS, "ops_per_ray": total_ops / n_rays,
+                     "bytes_per_ray": total_bytes / n_rays,
+                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved / HBM_PEAK_GBS}},
         "steps": args.steps, "timed_wall_s": wall,
         "scenes": [{"triangles": m["tris"], "rays": m["rays"], "grid": m["grid"],
                     "threshold": None if math.isinf(taus[k]) else taus[k], "error_rate": float(err[k])}

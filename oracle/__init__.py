@@ -12,6 +12,8 @@ Every function takes the exact FP32 inputs the GPU sees and computes in FP64:
   query         O-4  combined / triangles-only / DF-only query (Section 2, Eq. (2))
   margin        per-ray distance from a decision boundary, for parity filtering
   df_grad       O-6  d t_hit / d grid sample by implicit differentiation
+  sdf_grid_on_paths  O-5 samples only on the cells each ray's walk reaches
+                before its first root (for full-size parity tests)
 """
 from __future__ import annotations
 
