@@ -146,6 +146,7 @@ class Bvh:
 
     def __init__(self, handle):
         self._h = handle
+        self._L = lib()
         n_nodes, n_tris, depth = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         _check("hyb_bvh_info", lib().hyb_bvh_info(handle, ctypes.byref(n_nodes), ctypes.byref(n_tris),
                                                   ctypes.byref(depth)))
@@ -156,8 +157,10 @@ class Bvh:
         return self._h
 
     def __del__(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.hyb_bvh_destroy(self._h)
+        # destroyed by the library that made the handle
+        L = getattr(self, "_L", None)
+        if getattr(self, "_h", None) and L is not None:
+            L.hyb_bvh_destroy(self._h)
             self._h = None
 
 
@@ -166,6 +169,7 @@ class Sdf:
 
     def __init__(self, handle):
         self._h = handle
+        self._L = lib()
         g4 = (ctypes.c_float * 4)()
         n, L = ctypes.c_int32(), ctypes.c_float()
         _check("hyb_sdf_info", lib().hyb_sdf_info(handle, g4, ctypes.byref(n), ctypes.byref(L)))
@@ -185,8 +189,10 @@ class Sdf:
         return self._h
 
     def __del__(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.hyb_sdf_destroy(self._h)
+        # destroyed by the library that made the handle
+        L = getattr(self, "_L", None)
+        if getattr(self, "_h", None) and L is not None:
+            L.hyb_sdf_destroy(self._h)
             self._h = None
 
 
@@ -424,6 +430,7 @@ class Batch:
         h = ctypes.c_void_p()
         _check("hyb_batch_create", lib().hyb_batch_create(arr, len(items), _stream(stream), ctypes.byref(h)))
         self._h = h
+        self._L = lib()
         self.n_items = len(items)
 
     @property
@@ -469,6 +476,8 @@ class Batch:
         return err, ms.value
 
     def __del__(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.hyb_batch_destroy(self._h)
+        # destroyed by the library that made the handle
+        L = getattr(self, "_L", None)
+        if getattr(self, "_h", None) and L is not None:
+            L.hyb_batch_destroy(self._h)
             self._h = None

@@ -170,6 +170,7 @@ inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s
         a.lo_z = s->grid4[2];
         a.h = s->grid4[3];
         a.inv_h = 1.0f / s->grid4[3];
+        a.inv_hd = 1.0 / (double)s->grid4[3];
         a.inv_l = hyb::inv_step(s->lipschitz);
         a.two_e = (s->certified && s->fmt == HYB_SDF_F32) ? hyb::certified_slack(s->grid4[3], s->n) : __builtin_inff();
         a.slope_x = s->slope[0];

@@ -32,6 +32,7 @@ struct TraceArgs {
     // query
     float tmax, tau, tau_end;
     int64_t n;
+    double inv_hd;  // 1 / h in FP64 (scales the distance field's FP64 ray position)
 };
 
 hipError_t launch_trace(int mode, bool counters, const TraceArgs& a, hipStream_t stream);

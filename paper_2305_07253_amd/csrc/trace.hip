@@ -10,11 +10,20 @@
 
 namespace hyb {
 
-// One-cell F16 bricks: the compiler's 74 VGPRs allow six wavefronts per
-// SIMD; held to 72 they fit seven.
+// Wavefronts per SIMD the compiler is held to where that measured faster:
+// one-cell F16 bricks, 74 VGPRs left alone, fit seven at 72; the combined I8
+// query, 82, fits six at 80 (7% faster at threshold 1; the DF-only I8 kernel
+// held to 72 was 18% slower).
 template <int MODE, int FMT, bool COUNT>
-__global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(FMT == kF16 && !COUNT && (MODE == kCombined || MODE == kDfOnly) ? 7 : 1)))
+constexpr int trace_waves() {
+    if (COUNT) return 1;
+    if (FMT == kF16 && (MODE == kCombined || MODE == kDfOnly)) return 7;
+    if (FMT == kI8 && MODE == kCombined) return 6;
+    return 1;
+}
+
+template <int MODE, int FMT, bool COUNT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(trace_waves<MODE, FMT, COUNT>())))
 void k_trace(TraceArgs a) {
     extern __shared__ int s_stack[];
     const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x, kXcdRun) * kBlock + threadIdx.x;

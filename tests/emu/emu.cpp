@@ -160,7 +160,7 @@ int main(int argc, char** argv) {
     a.fmt = fmt;
     a.nb = (int)nb;
     a.n_grid = (int)N;
-    a.lo_x = par[2]; a.lo_y = par[3]; a.lo_z = par[4]; a.h = par[5]; a.inv_h = inv_h;
+    a.lo_x = par[2]; a.lo_y = par[3]; a.lo_z = par[4]; a.h = par[5]; a.inv_h = inv_h; a.inv_hd = 1.0 / (double)par[5];
     a.inv_l = hyb::inv_step(L);
     a.two_e = (par[6] != 0.0f && fmt == 0) ? hyb::certified_slack(par[5], (int)N) : __builtin_inff();
     a.slope_x = slope[0];
