@@ -57,11 +57,17 @@ typedef struct hyb_sdf_s* hyb_sdf; /* distance-field grid; library-owned device 
  * continuous.  Triangle tests and t comparisons stay FP32.
  *   HYB_SDF_F32       FP32 samples
  *   HYB_SDF_F16       IEEE half, round to nearest even; value = (float)half
- *   HYB_SDF_I8_BRICK  int8 per node plus one FP32 scale per 8^3 block of nodes
- *                     (node (i,j,k) belongs to block (i/8, j/8, k/8)):
- *                     scale = max |f| over the block / 127 (1 if that is 0),
- *                     q = rint(f / scale) clamped to [-127, 127] (FP32 division,
- *                     round half to even), value = q * scale (FP32).
+ *   HYB_SDF_I8_BRICK  int8 codes plus one power-of-two scale per block of
+ *                     8^3 cells (cells [8b, 8b + 8) on each axis, so nodes
+ *                     [8b, 8b + 8]: neighbouring blocks share a face of nodes;
+ *                     ceil((n - 1) / 8) blocks per axis).  Block scale 2^e
+ *                     with e the smallest integer >= -126 such that
+ *                     max |f| over the block's nodes <= 127 * 2^e.  A node in
+ *                     several blocks (on a face) takes the largest of their
+ *                     scales, s_max: value = q * s_max with q = rint(f / s_max)
+ *                     (round half to even) clamped to +-floor(127 s_min / s_max),
+ *                     s_min the smallest of them.  Each cell's 8 corners are then
+ *                     int8 multiples of its own block's scale.
  * Compact formats do not use the certified-sample step bound.  Inside the
  * library the kernels read a bricked copy in which every cell's 8 corner
  * samples lie together (bricks of 2^3 cells with their 3^3 nodes, padded to

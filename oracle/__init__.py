@@ -72,13 +72,45 @@ FMT_F32, FMT_F16, FMT_I8 = 0, 1, 2
 SCALE_BLOCK = 8
 
 
+def _block_exponents(g, nb):
+    """e_B of every block of 8^3 cells: the smallest integer e >= -126 with
+    max |f| over the block's nodes (cells [8b, 8b + 8) on each axis, so nodes
+    [8b, 8b + 8]) <= 127 * 2^e.  Exact: the bound is compared in FP64."""
+    n = g.shape[-1]
+    a = np.abs(g).astype(np.float64)
+    size = SCALE_BLOCK * nb + 1
+    a = np.pad(a, [(0, max(size - n, 0))] * 3)
+    for ax in range(3):
+        sl = [np.take(a, np.arange(off, off + SCALE_BLOCK * nb, SCALE_BLOCK), axis=ax) for off in range(SCALE_BLOCK + 1)]
+        a = np.maximum.reduce(sl)
+    m = a[:nb, :nb, :nb]
+    e = np.full(m.shape, -126, dtype=np.int64)
+    pos = m > 0
+    e[pos] = np.maximum(np.ceil(np.log2(m[pos] / 127.0)).astype(np.int64), -126)
+    # correct the logarithm's rounding: smallest e with m <= 127 2^e
+    low = pos & (np.ldexp(127.0, e) < m)
+    e[low] += 1
+    high = pos & (e > -126) & (np.ldexp(127.0, e - 1) >= m)
+    e[high] -= 1
+    assert np.all(m <= np.ldexp(127.0, e))
+    return e
+
+
 def quantize(grid, fmt):
     """Compact storage of an FP32 grid (n,n,n) [k,j,i], as the library defines
     it: returns (dequantized float32 grid, stored values, block scales or None).
       F16: round to nearest even half.
-      I8:  per 8^3 block of nodes (node (i,j,k) -> block (i//8, j//8, k//8)),
-           scale = max|f| / 127 in FP32 (1 if 0); q = rint(f / scale) in FP32,
-           clamped to [-127, 127]; value = q * scale in FP32."""
+      I8:  blocks of 8^3 cells (cells [8b, 8b + 8) on each axis, nodes
+           [8b, 8b + 8]: neighbouring blocks share a face of nodes), ceil((n - 1)
+           / 8) per axis.  Block scale s_B = 2^e_B (_block_exponents).  A node
+           lies in 1 to 8 blocks; with s_max and s_min the largest and smallest
+           of their scales, its code is q = rint(f / s_max) (exact division,
+           rounding half to even) clamped to +-floor(127 s_min / s_max), and its
+           value q s_max (exact in FP32).  In every block holding the node the
+           value is then an integer multiple k s_B with |k| <= 127, so a cell's
+           8 corners are stored as int8 multiples of the one scale of the cell's
+           block, and the interpolant stays continuous across block faces.
+           Returns the node codes q (int8) and the block scales (nb, nb, nb)."""
     g = np.ascontiguousarray(grid, dtype=np.float32)
     if fmt == FMT_F32:
         return g, g, None
@@ -86,14 +118,27 @@ def quantize(grid, fmt):
         h = g.astype(np.float16)
         return h.astype(np.float32), h, None
     n = g.shape[-1]
-    nb = (n + SCALE_BLOCK - 1) // SCALE_BLOCK
-    pad = nb * SCALE_BLOCK - n
-    a = np.pad(np.abs(g), ((0, pad), (0, pad), (0, pad)))
-    m = a.reshape(nb, SCALE_BLOCK, nb, SCALE_BLOCK, nb, SCALE_BLOCK).max(axis=(1, 3, 5)).astype(np.float32)
-    scales = np.where(m > 0, m / np.float32(127.0), np.float32(1.0)).astype(np.float32)
-    s = np.repeat(np.repeat(np.repeat(scales, SCALE_BLOCK, 0), SCALE_BLOCK, 1), SCALE_BLOCK, 2)[:n, :n, :n]
-    q = np.clip(np.rint(g / s), -127, 127).astype(np.float32)
-    return (q * s).astype(np.float32), q.astype(np.int8), scales
+    nb = max((n - 1 + SCALE_BLOCK - 1) // SCALE_BLOCK, 1)
+    e = _block_exponents(g, nb)
+    # the blocks holding node i along one axis: (i - 1) // 8 (when i is on a
+    # face) to i // 8, within [0, nb - 1]
+    idx = np.arange(n)
+    lo = np.clip((idx - 1) // SCALE_BLOCK, 0, nb - 1)
+    hi = np.clip(idx // SCALE_BLOCK, 0, nb - 1)
+    emax = np.full((n, n, n), -10 ** 6, dtype=np.int64)
+    emin = np.full((n, n, n), 10 ** 6, dtype=np.int64)
+    for bk in (lo, hi):
+        for bj in (lo, hi):
+            for bi in (lo, hi):
+                sub = e[np.ix_(bk, bj, bi)]
+                emax = np.maximum(emax, sub)
+                emin = np.minimum(emin, sub)
+    q = np.rint(np.ldexp(g, -emax).astype(np.float32))
+    lim = np.floor(np.ldexp(127.0, emin - emax))
+    q = np.clip(q, -lim, lim)
+    deq = np.ldexp(q, emax).astype(np.float32)
+    scales = np.ldexp(np.float32(1.0), e).astype(np.float32)
+    return deq, q.astype(np.int8), scales
 
 
 def threads() -> int:

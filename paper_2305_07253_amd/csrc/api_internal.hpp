@@ -118,11 +118,10 @@ inline hyb_status quantize(hyb_sdf_s* s, hipStream_t stream) {
     s->layout = fmt;
     const size_t count = static_cast<size_t>(hyb::brick_storage(fmt, s->n));
     const size_t elem = s->fmt == HYB_SDF_F32 ? 4 : (s->fmt == HYB_SDF_F16 ? 2 : 1);
-    s->nb = (s->n + hyb::kScaleBlock - 1) / hyb::kScaleBlock;
+    s->nb = hyb::i8_blocks(s->n);
     HYB_TRY(hipMalloc(&s->store, count * elem));
     if (s->fmt == HYB_SDF_I8_BRICK)
-        // one float of padding: the trace kernels load x-adjacent scales in pairs
-        HYB_TRY(hipMalloc(&s->scales, sizeof(float) * (static_cast<size_t>(s->nb) * s->nb * s->nb + 1)));
+        HYB_TRY(hipMalloc(&s->scales, sizeof(float) * static_cast<size_t>(s->nb) * s->nb * s->nb));
     return from_hip(hyb::launch_quantize(fmt, s->values, s->n, s->store, s->scales, stream));
 }
 

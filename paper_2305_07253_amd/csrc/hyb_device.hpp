@@ -291,11 +291,14 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
 // bricks of 2^3 cells that FP32 uses, for grids whose one-cell F16 copy would
 // crowd the 256 MB MALL (f16_layout).
 enum SdfFormat : int { kF32 = 0, kF16 = 1, kI8 = 2, kF16B2 = 3 };
-constexpr int kScaleBlock = 8;  // I8: one scale per 8^3 block of nodes
+constexpr int kScaleBlock = 8;  // I8: one scale per block of 8^3 cells
+
+// I8 scale blocks per axis of an n^3 grid: ceil((n - 1) / 8) blocks of cells.
+HYB_HD int i8_blocks(int n) { return (n - 1 + kScaleBlock - 1) / kScaleBlock; }
 
 struct Grid {
     const void* __restrict__ v;        // samples in the bricked layout Brick<FMT> (float, _Float16 or int8_t)
-    const float* __restrict__ scales;  // I8: per node block (node (i,j,k) -> block (i/8, j/8, k/8))
+    const float* __restrict__ scales;  // I8: per block of cells (cell (i,j,k) -> block (i/8, j/8, k/8))
     int n, nb;                         // samples per axis, scale blocks per axis
     float lo_x, lo_y, lo_z, h, inv_h;
     float inv_l;    // 1 / Lipschitz bound of the interpolant (slightly reduced)
@@ -398,26 +401,16 @@ HYB_HD void corners(const Grid& g, int i, int j, int k, float f[8]) {
         const _Float16* p = static_cast<const _Float16*>(g.v) + slot;
         for (int c = 0; c < 8; ++c) f[c] = (float)p[off[c]];
     } else {
+        // the 8 codes are multiples of the one scale of the cell's block
+        // (exact products: the scales are powers of two).  The table has at
+        // most 128^3 entries, so its byte offset is 32-bit, formed with 24-bit
+        // multiply-adds.
         const int8_t* p = static_cast<const int8_t*>(g.v) + slot;
-        const uint32_t nb = (uint32_t)g.nb;
-        const uint32_t bi0 = (uint32_t)i / kScaleBlock;
-        const uint32_t bj0 = (uint32_t)j / kScaleBlock, bj1 = (uint32_t)(j + 1) / kScaleBlock;
-        const uint32_t bk0 = (uint32_t)k / kScaleBlock, bk1 = (uint32_t)(k + 1) / kScaleBlock;
-        // the scales of x-adjacent blocks are adjacent: one pair per (y, z) of
-        // the corners, the second taken when the cell crosses an x block face
-        // (the table holds one float of padding past the last block).  The
-        // table has at most 128^3 entries, so block indices and byte offsets
-        // are 32-bit, formed with 24-bit multiply-adds.
-        const bool cross_x = ((uint32_t)i % kScaleBlock) == kScaleBlock - 1;
-        const char* sb = reinterpret_cast<const char*>(g.scales);
-        const uint32_t nb4 = 4u * nb, nbb4 = nb4 * nb, x4 = 4u * bi0;
-        for (int c = 0; c < 8; c += 2) {
-            const uint32_t bj = (c & 2) ? bj1 : bj0, bk = (c & 4) ? bk1 : bk0;
-            const float* sp = reinterpret_cast<const float*>(sb + mad24(bk, nbb4, mad24(bj, nb4, x4)));
-            const float s0 = sp[0], s1 = sp[1];
-            f[c] = (float)p[off[c]] * s0;
-            f[c + 1] = (float)p[off[c + 1]] * (cross_x ? s1 : s0);
-        }
+        const uint32_t nb4 = 4u * (uint32_t)g.nb, nbb4 = nb4 * (uint32_t)g.nb;
+        const uint32_t bi = (uint32_t)i / kScaleBlock, bj = (uint32_t)j / kScaleBlock, bk = (uint32_t)k / kScaleBlock;
+        const float s = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(g.scales) +
+                                                        mad24(bk, nbb4, mad24(bj, nb4, 4u * bi)));
+        for (int c = 0; c < 8; ++c) f[c] = (float)p[off[c]] * s;
     }
 }
 

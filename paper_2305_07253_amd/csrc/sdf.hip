@@ -49,18 +49,32 @@ __global__ __launch_bounds__(256) void k_lipschitz(const float* __restrict__ g, 
     if (threadIdx.x < V) block_max[V * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// I8 block scales: one thread per 8^3 block of nodes, max |f| / 127.
+// I8 block scales: one thread per block of 8^3 cells (its nodes [8b, 8b + 8]
+// on each axis, a face shared with the next block): 2^e with e the smallest
+// integer >= -126 such that max |f| <= 127 * 2^e (exact comparisons).
 __global__ __launch_bounds__(256) void k_block_scales(const float* __restrict__ in, int32_t n, int32_t nb,
                                                       float* __restrict__ scales) {
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (b >= (int64_t)nb * nb * nb) return;
     const int bi = (int)(b % nb), bj = (int)((b / nb) % nb), bk = (int)(b / ((int64_t)nb * nb));
     float m = 0.0f;
-    for (int k = bk * kScaleBlock; k < min(n, (bk + 1) * kScaleBlock); ++k)
-        for (int j = bj * kScaleBlock; j < min(n, (bj + 1) * kScaleBlock); ++j)
-            for (int i = bi * kScaleBlock; i < min(n, (bi + 1) * kScaleBlock); ++i)
+    for (int k = bk * kScaleBlock; k <= min(n - 1, (bk + 1) * kScaleBlock); ++k)
+        for (int j = bj * kScaleBlock; j <= min(n - 1, (bj + 1) * kScaleBlock); ++j)
+            for (int i = bi * kScaleBlock; i <= min(n - 1, (bi + 1) * kScaleBlock); ++i)
                 m = fmaxf(m, fabsf(in[i + (int64_t)n * (j + (int64_t)n * k)]));
-    scales[b] = m > 0.0f ? m / 127.0f : 1.0f;
+    int e = -126;
+    if (m > 0.0f) {
+        e = max(ilogbf(m) - 7, -126);  // 127 * 2^e < m here: 127 < 2^7
+        while (ldexpf(127.0f, e) < m) ++e;
+    }
+    scales[b] = ldexpf(1.0f, e);
+}
+
+// The I8 blocks holding node i along one axis: lo to hi (equal unless the
+// node lies on a face between two blocks).
+__device__ inline void node_blocks(int i, int nb, int& lo, int& hi) {
+    lo = min(max((i - 1) / kScaleBlock, 0), nb - 1);
+    hi = min(i / kScaleBlock, nb - 1);
 }
 
 // One storage slot of the bricked layout: the sample of its node in the
@@ -76,10 +90,15 @@ __device__ void store_slot(const float* __restrict__ in, int32_t n, int32_t nb, 
     } else if constexpr (FMT == kF16 || FMT == kF16B2) {
         static_cast<_Float16*>(out)[s] = (_Float16)f;
     } else {
+        // `in` holds the dequantized values: a node's value is an integer
+        // multiple of the scale of every block holding it, here the block of
+        // the slot's cell (one-cell bricks: brick = cell)
         float q = 0.0f;
         if (node) {
-            const float sc = scales[i / kScaleBlock + nb * (j / kScaleBlock + nb * (k / kScaleBlock))];
-            q = fminf(fmaxf(rintf(f / sc), -127.0f), 127.0f);
+            const int64_t b = s / Brick<kI8>::kStride;
+            const int nc = Brick<kI8>::per_axis(n);
+            const int ci = (int)(b % nc), cj = (int)((b / nc) % nc), ck = (int)(b / ((int64_t)nc * nc));
+            q = f / scales[ci / kScaleBlock + nb * (cj / kScaleBlock + nb * (ck / kScaleBlock))];
         }
         static_cast<int8_t*>(out)[s] = (int8_t)q;
     }
@@ -106,9 +125,24 @@ __global__ __launch_bounds__(256) void k_dequantize(float* __restrict__ values, 
     if constexpr (FMT == kF16) {
         values[id] = (float)(_Float16)f;
     } else {
+        // the largest and smallest scale of the 1 to 8 blocks holding the
+        // node: code rint(f / s_max), clamped to what the smallest-scale
+        // block can hold, times s_max (all exact: powers of two)
         const int i = (int)(id % nn), j = (int)((id / nn) % nn), k = (int)(id / (nn * nn));
-        const float sc = scales[i / kScaleBlock + nb * (j / kScaleBlock + nb * (k / kScaleBlock))];
-        values[id] = fminf(fmaxf(rintf(f / sc), -127.0f), 127.0f) * sc;
+        int il, ih, jl, jh, kl, kh;
+        node_blocks(i, nb, il, ih);
+        node_blocks(j, nb, jl, jh);
+        node_blocks(k, nb, kl, kh);
+        float smax = 0.0f, smin = __builtin_inff();
+        for (int bk = kl; bk <= kh; ++bk)
+            for (int bj = jl; bj <= jh; ++bj)
+                for (int bi = il; bi <= ih; ++bi) {
+                    const float sc = scales[bi + nb * (bj + nb * bk)];
+                    smax = fmaxf(smax, sc);
+                    smin = fminf(smin, sc);
+                }
+        const float lim = floorf(127.0f * (smin / smax));
+        values[id] = fminf(fmaxf(rintf(f / smax), -lim), lim) * smax;
     }
 }
 
@@ -119,7 +153,7 @@ hipError_t launch_quantize(int fmt, float* values, int32_t n, void* out, float* 
     const unsigned blocks = (unsigned)((total + 255) / 256);
     const int64_t slots = brick_storage(fmt, n);
     const unsigned sblocks = (unsigned)std::min<int64_t>((slots + 255) / 256, int64_t(1) << 20);
-    const int32_t nb = (n + kScaleBlock - 1) / kScaleBlock;
+    const int32_t nb = i8_blocks(n);
     if (fmt == kF32) {
         hipLaunchKernelGGL(k_store<kF32>, dim3(sblocks), dim3(256), 0, stream, values, n, nb, slots, out, scales);
     } else if (fmt == kF16) {
@@ -132,8 +166,8 @@ hipError_t launch_quantize(int fmt, float* values, int32_t n, void* out, float* 
         const int64_t nbb = (int64_t)nb * nb * nb;
         hipLaunchKernelGGL(k_block_scales, dim3((unsigned)((nbb + 255) / 256)), dim3(256), 0, stream, values, n, nb,
                            scales);
-        hipLaunchKernelGGL(k_store<kI8>, dim3(sblocks), dim3(256), 0, stream, values, n, nb, slots, out, scales);
         hipLaunchKernelGGL(k_dequantize<kI8>, dim3(blocks), dim3(256), 0, stream, values, n, nb, scales);
+        hipLaunchKernelGGL(k_store<kI8>, dim3(sblocks), dim3(256), 0, stream, values, n, nb, slots, out, scales);
     } else {
         return hipErrorInvalidValue;
     }

@@ -10,9 +10,11 @@
 //         flag: exterior solid (what 1) / certified 1-Lipschitz samples (what 0)
 //         verts f32[3 n_verts], tris i32[3 n_tris],
 //         grid (what 0, N > 0): f32[N^3] dequantized values, then the stored
-//           values (f16 or i8 [N^3]) and f32 block scales [nb^3] for fmt 1/2
-//           (fmt 3: the f16 values laid out in the two-cell bricks of large grids),
-//           all x fastest (the emulator lays them out in bricks),
+//           f16 values [N^3] for fmt 1 and 3 (fmt 3: laid out in the two-cell
+//           bricks of large grids), the f32 block scales [nb^3] (blocks of 8^3
+//           cells) for fmt 2, all x fastest (the emulator lays them out in
+//           bricks; I8 codes are the dequantized values over the scale of
+//           the cell's block),
 //         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays], tmax f32[n_rays]
 // what 0 (trace): output t f32[n], prim i32[n], u f32[n], v f32[n], counts i32[3n]
 // what 1 (sdf):   output f32[N^3] signed distances of the grid nodes
@@ -57,14 +59,12 @@ int main(int argc, char** argv) {
     }
     const long long what = hdr[0], n = hdr[1], nv = hdr[2], nt = hdr[3], N = hdr[4], has_tmin = hdr[5], mode = hdr[6];
     const int fmt = (int)hdr[7];
-    const long long nb = (N + hyb::kScaleBlock - 1) / hyb::kScaleBlock;
+    const long long nb = N > 1 ? hyb::i8_blocks((int)N) : 0;
     auto verts = rd<float>(f, 3 * nv);
     auto tris = rd<int32_t>(f, 3 * nt);
     std::vector<float> grid = what != 1 && N > 0 ? rd<float>(f, N * N * N) : std::vector<float>();
     std::vector<_Float16> g16 = what == 0 && N > 0 && (fmt == 1 || fmt == 3) ? rd<_Float16>(f, N * N * N) : std::vector<_Float16>();
-    std::vector<int8_t> g8 = what == 0 && N > 0 && fmt == 2 ? rd<int8_t>(f, N * N * N) : std::vector<int8_t>();
     std::vector<float> scales = what == 0 && N > 0 && fmt == 2 ? rd<float>(f, nb * nb * nb) : std::vector<float>();
-    if (!scales.empty()) scales.push_back(0.0f);  // the padding float the library allocates
     auto rays = rd<float>(f, 6 * n);
     auto tmin = (has_tmin & 1) ? rd<float>(f, n) : std::vector<float>();
     auto tmaxr = (has_tmin & 2) ? rd<float>(f, n) : std::vector<float>();
@@ -124,7 +124,7 @@ int main(int argc, char** argv) {
     const size_t n8 = N > 0 ? (size_t)hyb::Brick<hyb::kI8>::storage((int)N) : 0;
     std::vector<float> b32(grid.empty() ? 0 : n32, 0.0f);
     std::vector<_Float16> b16(g16.empty() ? 0 : n16, (_Float16)0.0f);
-    std::vector<int8_t> b8(g8.empty() ? 0 : n8, 0);
+    std::vector<int8_t> b8(scales.empty() ? 0 : n8, 0);
     int i, j, k;
     for (size_t s = 0; s < b32.size(); ++s)
         if (hyb::Brick<hyb::kF32>::slot_node((int64_t)s, (int)N, i, j, k)) b32[s] = grid.at(i + N * (j + N * (long long)k));
@@ -133,7 +133,14 @@ int main(int argc, char** argv) {
                      : hyb::Brick<hyb::kF16>::slot_node((int64_t)s, (int)N, i, j, k))
             b16[s] = g16.at(i + N * (j + N * (long long)k));
     for (size_t s = 0; s < b8.size(); ++s)
-        if (hyb::Brick<hyb::kI8>::slot_node((int64_t)s, (int)N, i, j, k)) b8[s] = g8.at(i + N * (j + N * (long long)k));
+        if (hyb::Brick<hyb::kI8>::slot_node((int64_t)s, (int)N, i, j, k)) {
+            const long long b = (long long)s / hyb::Brick<hyb::kI8>::kStride, nc = N - 1;
+            const long long ci = b % nc, cj = (b / nc) % nc, ck = b / (nc * nc);
+            const float sc = scales.at(ci / 8 + nb * (cj / 8 + nb * (ck / 8)));
+            const float q = grid.at(i + N * (j + N * (long long)k)) / sc;
+            if (!(q == (float)(int)q && q >= -127.0f && q <= 127.0f)) return 5;  // not a code of this block
+            b8[s] = (int8_t)q;
+        }
 
     std::vector<float> t(n), u(n), v(n);
     std::vector<int32_t> prim(n), counts(3 * n);

@@ -79,7 +79,6 @@ def trace(verts, tris, grid, grid4, rays_soa, tmax, tau, mode=0, tmin=None, cert
         if fmt in (1, 3):
             arrays.append(stored.astype(np.float16))
         elif fmt == 2:
-            arrays.append(stored.astype(np.int8))
             arrays.append(scales.astype(np.float32))
     arrays.append(rays_soa)
     if tmin is not None:

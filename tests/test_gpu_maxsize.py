@@ -8,7 +8,9 @@ The field is the exact FP32 signed distance to a sphere (centre 0.5, radius
 k ~ 819, far into the upper half of every store) and are short enough that each
 segment stays inside a 160^3-node window aligned to the 8^3 scale blocks; the
 oracle gets that window of the same FP32 samples (dequantized by its own rule
-for F16 and I8), so its first root equals the one on the full grid.
+for F16 and I8, from a window one scale block larger below and one node
+larger above, so every window node sees all the blocks holding it), so its
+first root equals the one on the full grid.
 """
 import numpy as np
 import pytest
@@ -79,9 +81,14 @@ def test_max_grid_size_parity(hyb, orc, sphere_grid, rays, fmt):
     del sdf
     torch.cuda.empty_cache()
     k0, j0, i0 = WIN
-    win = np.ascontiguousarray(sphere_grid[k0:k0 + WSIZE, j0:j0 + WSIZE, i0:i0 + WSIZE])
     if fmt:
-        win = orc.quantize(win, fmt)[0]
+        # an I8 node's value depends on the scale blocks holding it: quantize
+        # the window grown by one block below and one node above (whole blocks
+        # around every window node, aligned as in the full grid), then crop
+        big = np.ascontiguousarray(sphere_grid[k0 - 8:k0 + WSIZE + 1, j0 - 8:j0 + WSIZE + 1, i0 - 8:i0 + WSIZE + 1])
+        win = np.ascontiguousarray(orc.quantize(big, fmt)[0][8:8 + WSIZE, 8:8 + WSIZE, 8:8 + WSIZE])
+    else:
+        win = np.ascontiguousarray(sphere_grid[k0:k0 + WSIZE, j0:j0 + WSIZE, i0:i0 + WSIZE])
     g4 = np.array([i0 * H, j0 * H, k0 * H, H], dtype=np.float32)
     ref = orc.query(None, np.zeros((0, 3)), win, g4, rays, TMAX, 0.0, mode=orc.MODE_DF)
     m, c = orc.margin(None, np.zeros((0, 3)), win, g4, rays, TMAX, 0.0, mode=orc.MODE_DF)

@@ -510,21 +510,49 @@ def test_quantize_f16_error_bound(orc, tiny):
 
 
 def test_quantize_i8_blocks_and_bound(orc, tiny):
-    g = tiny["grid"]
-    n = g.shape[0]
-    deq, q, scales = orc.quantize(g, orc.FMT_I8)
-    nb = (n + 7) // 8
-    assert scales.shape == (nb, nb, nb) and q.dtype == np.int8
+    """The I8 rule checked block by block and node by node with plain loops:
+    each block's scale is the smallest power of two (exponent >= -126) whose
+    127 multiple bounds the block's largest |f| (its 9^3 nodes, faces shared);
+    every node's value is an int8 multiple of the scale of each block holding
+    it (so a cell's 8 corners share its block's scale); the error is at most
+    half a step of the node's largest scale, or one step where the smallest
+    scale's range clamps it."""
     rng = np.random.default_rng(13)
-    for _ in range(200):
+    g = tiny["grid"].copy()
+    n = g.shape[0]
+    # one loud node on a block face: its neighbouring blocks get much larger
+    # scales than the quiet ones beside them
+    g[16, 16, 16] = 50.0
+    deq, q, scales = orc.quantize(g, orc.FMT_I8)
+    nb = (n - 1 + 7) // 8
+    assert scales.shape == (nb, nb, nb) and q.dtype == np.int8
+    ext = lambda b: range(8 * b, min(8 * b + 8, n - 1) + 1)
+    for bk in range(nb):
+        for bj in range(nb):
+            for bi in range(nb):
+                s = float(scales[bk, bj, bi])
+                e = int(np.log2(s))
+                assert s == 2.0 ** e and e >= -126
+                m = max(abs(float(g[k, j, i])) for k in ext(bk) for j in ext(bj) for i in ext(bi))
+                assert m <= 127 * s and (e == -126 or m > 127 * s / 2)
+                for k in ext(bk):
+                    for j in ext(bj):
+                        for i in ext(bi):
+                            c = float(deq[k, j, i]) / s
+                            assert c == round(c) and abs(c) <= 127
+    holders = lambda i: sorted({min(max((i - 1) // 8, 0), nb - 1), min(i // 8, nb - 1)})
+    for _ in range(400):
         k, j, i = rng.integers(0, n, 3)
-        s = scales[k // 8, j // 8, i // 8]
-        # the node's own block scale; the largest |f| of the block maps to +-127
-        blk = g[k // 8 * 8:k // 8 * 8 + 8, j // 8 * 8:j // 8 * 8 + 8, i // 8 * 8:i // 8 * 8 + 8]
-        assert s == np.float32(np.abs(blk).max()) / np.float32(127)
-        assert abs(float(deq[k, j, i]) - float(g[k, j, i])) <= 0.5 * s * (1 + 1e-6) + 1e-9
-        assert deq[k, j, i] == np.float32(q[k, j, i]) * s
-    assert np.abs(q).max() == 127
+        ss = [float(scales[a, b, c]) for a in holders(k) for b in holders(j) for c in holders(i)]
+        smax, smin = max(ss), min(ss)
+        lim = np.floor(127 * smin / smax)
+        code = np.float32(g[k, j, i]) / np.float32(smax)
+        clamped = abs(np.rint(code)) > lim
+        err = abs(float(deq[k, j, i]) - float(g[k, j, i]))
+        assert err <= (1.0 if clamped else 0.5) * smax
+        assert deq[k, j, i] == np.float32(q[k, j, i]) * np.float32(smax)
+    # power-of-two scales: a block's largest value takes a code in (63.5, 127]
+    assert 63 < np.abs(q.astype(np.int32)).max() <= 127
 
 
 def test_quantized_interpolant_stays_continuous(orc, tiny):
