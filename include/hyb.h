@@ -125,6 +125,8 @@ typedef struct {
  * g / L.  Grids from hyb_build_sdf carry this property implicitly.  A false
  * certification can make the tracer pass a root. */
 #define HYB_SDF_LIPSCHITZ_SAMPLES 2u
+/* hyb_sdf_update flag: do not wait for the device (see hyb_sdf_update). */
+#define HYB_SDF_UPDATE_DEFERRED 4u
 
 /* Build a BVH over an indexed triangle mesh (the structure the paper's
  * hardware ray tracing traverses, Section 3).
@@ -185,15 +187,31 @@ hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4,
  * give for its own n, grid4 and format, bounds included, in the device memory
  * it already owns (nothing is allocated).
  *   values  device, n^3 floats of the handle's n, x fastest
- *   flags   0 or HYB_SDF_LIPSCHITZ_SAMPLES
+ *   flags   0 or HYB_SDF_LIPSCHITZ_SAMPLES, optionally with
+ *           HYB_SDF_UPDATE_DEFERRED
  * Synchronous on `stream` (the bounds are read back).  Work already queued on
  * other streams that reads the handle must have finished.  Batches that hold
  * the handle use the new samples and bounds from their next launch on.
+ * With HYB_SDF_UPDATE_DEFERRED the call only queues the work on `stream` and
+ * returns: the bounds stay on the device and later calls on the handle read
+ * them there (the same values, so the same results), so a loop that updates a
+ * grid every step need not wait for the device.  The check for samples that
+ * are not finite then happens on the device too: until the next update every
+ * query on the handle other than hyb_trace_bvh reports t = NaN, prim = -2 for
+ * every ray, hyb_df_backward adds nothing, and hyb_sdf_check reports it.
+ * hyb_sdf_info waits for the device to return the bound of such an update.
  * Errors: HYB_ERR_INVALID_ARG for a NULL handle/values, unknown flags, a
  * handle of another device, or a sample that is NaN or infinite (or, for
  * HYB_SDF_F16, beyond the half range); the handle's samples are then undefined
  * until the next successful update. */
 hyb_status hyb_sdf_update(hyb_sdf sdf, const float* values, uint32_t flags, void* stream);
+
+/* Whether the grid's last update (with HYB_SDF_UPDATE_DEFERRED) had only
+ * finite samples: waits for `stream` (the update's), then HYB_OK, or
+ * HYB_ERR_INVALID_ARG when a sample was NaN or infinite (or, for HYB_SDF_F16,
+ * beyond the half range) or for a NULL handle.  HYB_OK after any other
+ * update (those check synchronously). */
+hyb_status hyb_sdf_check(hyb_sdf sdf, void* stream);
 
 /* Voxel size h of the grid: the unit of the switch thresholds (Section 3,
  * "Occlusion Queries": t1 is computed from the voxel size times a user

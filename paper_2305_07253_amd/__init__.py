@@ -29,6 +29,7 @@ HYB_MISS = -1
 HYB_DF_HIT = -2
 EXTERIOR_SOLID = 1
 LIPSCHITZ_SAMPLES = 2
+UPDATE_DEFERRED = 4
 SDF_F32, SDF_F16, SDF_I8_BRICK = 0, 1, 2
 MODE_COMBINED, MODE_BVH, MODE_DF, MODE_SHADOW = 0, 1, 2, 3
 
@@ -87,6 +88,7 @@ def lib() -> ctypes.CDLL:
             "hyb_sdf_update": [P, P, u32, P],
             "hyb_sdf_info": [P, P, P, P],
             "hyb_sdf_voxel_size": [P, P],
+            "hyb_sdf_check": [P, P],
             "hyb_sdf_read": [P, P, P],
             "hyb_trace": [P, P, P, i64, f32, f32, P, P],
             "hyb_trace_bvh": [P, P, i64, f32, P, P],
@@ -171,11 +173,23 @@ class Sdf:
         self._h = handle
         self._L = lib()
         g4 = (ctypes.c_float * 4)()
-        n, L = ctypes.c_int32(), ctypes.c_float()
-        _check("hyb_sdf_info", lib().hyb_sdf_info(handle, g4, ctypes.byref(n), ctypes.byref(L)))
+        n = ctypes.c_int32()
+        _check("hyb_sdf_info", lib().hyb_sdf_info(handle, g4, ctypes.byref(n), None))
         self.grid4 = np.array(list(g4), dtype=np.float32)
         self.n = n.value
-        self.lipschitz = L.value
+
+    @property
+    def lipschitz(self) -> float:
+        """Lipschitz bound of the stored samples' interpolant (hyb_sdf_info;
+        waits for the device after a deferred update)."""
+        L = ctypes.c_float()
+        _check("hyb_sdf_info", lib().hyb_sdf_info(self._h, None, None, ctypes.byref(L)))
+        return L.value
+
+    def check(self, stream=None):
+        """Raises HybError if the last deferred update had a sample that is
+        not finite (hyb_sdf_check; waits for the stream)."""
+        _check("hyb_sdf_check", lib().hyb_sdf_check(self._h, _stream(stream)))
 
     @property
     def h(self) -> float:
@@ -235,19 +249,19 @@ def sdf_from_grid(values, grid4, lipschitz_samples: bool = False, fmt: int = SDF
     return Sdf(out)
 
 
-def sdf_update(sdf: Sdf, values, lipschitz_samples: bool = False, stream=None) -> Sdf:
+def sdf_update(sdf: Sdf, values, lipschitz_samples: bool = False, stream=None, deferred: bool = False) -> Sdf:
     """Replace the samples of `sdf` in place by a CUDA float32 tensor of its
-    n^3 samples (x fastest), reusing its device memory; returns sdf."""
+    n^3 samples (x fastest), reusing its device memory; returns sdf.
+    deferred: queue the work on the stream without waiting for the device
+    (HYB_SDF_UPDATE_DEFERRED; non-finite samples then show as NaN hits and
+    through sdf.check())."""
     torch = _torch()
     if not (values.is_cuda and values.dtype == torch.float32 and values.is_contiguous()):
         raise ValueError("values must be a contiguous float32 CUDA tensor")
     if values.numel() != sdf.n ** 3:
         raise ValueError("values must hold the grid's n^3 samples")
-    _check("hyb_sdf_update", lib().hyb_sdf_update(sdf.handle, _ptr(values),
-                                                  LIPSCHITZ_SAMPLES if lipschitz_samples else 0, _stream(stream)))
-    L = ctypes.c_float()
-    _check("hyb_sdf_info", lib().hyb_sdf_info(sdf.handle, None, None, ctypes.byref(L)))
-    sdf.lipschitz = L.value
+    flags = (LIPSCHITZ_SAMPLES if lipschitz_samples else 0) | (UPDATE_DEFERRED if deferred else 0)
+    _check("hyb_sdf_update", lib().hyb_sdf_update(sdf.handle, _ptr(values), flags, _stream(stream)))
     return sdf
 
 

@@ -9,9 +9,11 @@ recomputed from the saved t rather than a stored ray path.  Lets a distance
 field be refit against triangle-hit targets to shrink its artefacts.
 
 With `sdf` given (a grid of theta's size and format), the forward writes theta
-into that handle with hyb_sdf_update instead of creating a grid per call; the
-backward then reads the handle, so it must run before the next forward that
-updates the same handle (the usual forward, backward, step loop).
+into that handle with a deferred hyb_sdf_update instead of creating a grid per
+call (nothing waits for the device; a non-finite theta gives NaN hits, and
+sdf.check() raises); the backward then reads the handle, so it must run before
+the next forward that updates the same handle (the usual forward, backward,
+step loop).
 """
 from __future__ import annotations
 
@@ -25,7 +27,7 @@ class DFHit(torch.autograd.Function):
     def forward(ctx, theta, grid4, rays, tmax, tmin=None, sdf=None):
         n = round(theta.numel() ** (1.0 / 3.0))
         values = theta.detach().contiguous().reshape(-1)
-        sdf = sdf_from_grid(values, grid4) if sdf is None else sdf_update(sdf, values)
+        sdf = sdf_from_grid(values, grid4) if sdf is None else sdf_update(sdf, values, deferred=True)
         t, prim, _, _ = trace_df(sdf, rays, tmax, tmin=tmin)
         ctx.sdf, ctx.tmax, ctx.n = sdf, float(tmax), n
         ctx.save_for_backward(rays, t, tmin if tmin is not None else torch.empty(0, device=t.device))

@@ -134,6 +134,7 @@ hyb_status hyb_build_sdf(hyb_bvh bvh, int32_t n, const float* grid4, uint32_t fl
     }
     hyb_status rc = from_hip(e);
     if (rc == HYB_OK) rc = quantize(s, st);
+    if (rc == HYB_OK) rc = from_hip(hipMalloc(&s->dev_bounds, sizeof(float) * hyb::kDeviceBounds));
     if (rc == HYB_OK) rc = compute_lipschitz(s, st);
     if (rc != HYB_OK) {
         hyb_sdf_destroy(s);
@@ -164,6 +165,7 @@ hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4,
     // the compact formats would turn a NaN input into a finite code
     if (rc == HYB_OK && fmt != HYB_SDF_F32) rc = check_finite(s, st);
     if (rc == HYB_OK) rc = quantize(s, st);
+    if (rc == HYB_OK) rc = from_hip(hipMalloc(&s->dev_bounds, sizeof(float) * hyb::kDeviceBounds));
     if (rc == HYB_OK) rc = compute_lipschitz(s, st);
     if (rc != HYB_OK) {
         hyb_sdf_destroy(s);
@@ -174,12 +176,14 @@ hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4,
 }
 
 hyb_status hyb_sdf_update(hyb_sdf sdf, const float* values, uint32_t flags, void* stream) {
-    if (!sdf || !values || (flags & ~HYB_SDF_LIPSCHITZ_SAMPLES) || !same_device(sdf->device))
+    if (!sdf || !values || (flags & ~(HYB_SDF_LIPSCHITZ_SAMPLES | HYB_SDF_UPDATE_DEFERRED)) ||
+        !same_device(sdf->device))
         return HYB_ERR_INVALID_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t bytes = sizeof(float) * static_cast<size_t>(sdf->n) * sdf->n * sdf->n;
     sdf->certified = (flags & HYB_SDF_LIPSCHITZ_SAMPLES) != 0;
     HYB_TRY(hipMemcpyAsync(sdf->values, values, bytes, hipMemcpyDeviceToDevice, st));
+    if (flags & HYB_SDF_UPDATE_DEFERRED) return deferred_bounds(sdf, st);
     if (sdf->fmt != HYB_SDF_F32) {
         // the compact formats would turn a NaN input into a finite code
         const hyb_status rc = check_finite(sdf, st);
@@ -199,8 +203,26 @@ hyb_status hyb_sdf_info(hyb_sdf sdf, float* grid4, int32_t* n, float* lipschitz)
     if (!sdf) return HYB_ERR_INVALID_ARG;
     if (grid4) std::memcpy(grid4, sdf->grid4, sizeof(sdf->grid4));
     if (n) *n = sdf->n;
-    if (lipschitz) *lipschitz = sdf->lipschitz;
+    if (lipschitz) {
+        if (sdf->deferred) {
+            // the bound of a deferred update is on the device
+            HYB_TRY(hipDeviceSynchronize());
+            HYB_TRY(hipMemcpy(&sdf->lipschitz, sdf->dev_bounds + hyb::kBLipschitz, sizeof(float),
+                              hipMemcpyDeviceToHost));
+        }
+        *lipschitz = sdf->lipschitz;
+    }
     return HYB_OK;
+}
+
+hyb_status hyb_sdf_check(hyb_sdf sdf, void* stream) {
+    if (!sdf) return HYB_ERR_INVALID_ARG;
+    if (!sdf->deferred) return HYB_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float bad = 0.0f;
+    HYB_TRY(hipMemcpyAsync(&bad, sdf->dev_bounds + hyb::kBBad, sizeof(float), hipMemcpyDeviceToHost, st));
+    HYB_TRY(hipStreamSynchronize(st));
+    return bad != 0.0f ? HYB_ERR_INVALID_ARG : HYB_OK;
 }
 
 hyb_status hyb_sdf_read(hyb_sdf sdf, float* out, void* stream) {
@@ -215,6 +237,7 @@ hyb_status hyb_sdf_destroy(hyb_sdf sdf) {
     if (sdf->store) (void)hipFree(sdf->store);
     if (sdf->scales) (void)hipFree(sdf->scales);
     if (sdf->blocks) (void)hipFree(sdf->blocks);
+    if (sdf->dev_bounds) (void)hipFree(sdf->dev_bounds);
     delete sdf;
     return HYB_OK;
 }

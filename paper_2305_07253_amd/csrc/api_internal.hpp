@@ -40,6 +40,8 @@ struct hyb_sdf_s {
     int32_t layout = 0;  // the kernels' storage format and brick layout (hyb::SdfFormat)
     float* blocks = nullptr;  // per-block maxima of the bound pass (kept for updates)
     uint64_t version = 0;     // bumped whenever the samples and bounds change (batches re-read them)
+    float* dev_bounds = nullptr;  // hyb::kDeviceBounds floats: the bounds of a deferred update
+    bool deferred = false;        // the last update was deferred: the kernels read dev_bounds
 };
 
 namespace hyb_api {
@@ -106,6 +108,32 @@ inline hyb_status compute_lipschitz(hyb_sdf_s* s, hipStream_t stream) {
     if (m[4] != 0.0f) return HYB_ERR_INVALID_ARG;
     s->lipschitz = hyb::finish_lipschitz(m[0]);
     for (int c = 0; c < 3; ++c) s->slope[c] = hyb::finish_slope(m[1 + c]);
+    s->deferred = false;
+    ++s->version;
+    return HYB_OK;
+}
+
+// The certified-grid step slack of the kernels, or +inf.
+inline float two_e_of(const hyb_sdf_s* s) {
+    return (s->certified && s->fmt == HYB_SDF_F32) ? hyb::certified_slack(s->grid4[3], s->n) : __builtin_inff();
+}
+
+// The bounds of compute_lipschitz (and check_finite for the compact formats,
+// on the input before it is quantized) left on the device for the kernels,
+// without waiting: the quantization runs between the two passes.
+inline hyb_status deferred_bounds(hyb_sdf_s* s, hipStream_t stream) {
+    const int32_t nb = hyb::lipschitz_blocks(s->n);
+    if (!s->blocks) HYB_TRY(hipMalloc(&s->blocks, sizeof(float) * hyb::kBoundValues * nb));
+    int32_t got = 0;
+    if (s->fmt != HYB_SDF_F32) {
+        HYB_TRY(hyb::launch_lipschitz(s->values, s->n, s->grid4[3], s->blocks, &got, stream));
+        HYB_TRY(hyb::launch_finish_bounds(s->blocks, got, 0, 0.0f, s->dev_bounds, stream));
+    }
+    HYB_TRY(hyb::launch_quantize(s->layout, s->values, s->n, s->store, s->scales, stream));
+    HYB_TRY(hyb::launch_lipschitz(s->values, s->n, s->grid4[3], s->blocks, &got, stream));
+    HYB_TRY(hyb::launch_finish_bounds(s->blocks, got, s->fmt != HYB_SDF_F32 ? 1 : 2, two_e_of(s), s->dev_bounds,
+                                      stream));
+    s->deferred = true;
     ++s->version;
     return HYB_OK;
 }
@@ -171,7 +199,8 @@ inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s
         a.inv_h = 1.0f / s->grid4[3];
         a.inv_hd = 1.0 / (double)s->grid4[3];
         a.inv_l = hyb::inv_step(s->lipschitz);
-        a.two_e = (s->certified && s->fmt == HYB_SDF_F32) ? hyb::certified_slack(s->grid4[3], s->n) : __builtin_inff();
+        a.two_e = two_e_of(s);
+        a.bounds = s->deferred ? s->dev_bounds : nullptr;
         a.slope_x = s->slope[0];
         a.slope_y = s->slope[1];
         a.slope_z = s->slope[2];

@@ -19,8 +19,7 @@ __global__ __launch_bounds__(256) void k_df_backward(TraceArgs a, const float* _
     const float tmin = a.tmin ? a.tmin[i] : 0.0f;
     const float tmax = a.tmax_ray ? fminf(a.tmax_ray[i], a.tmax) : a.tmax;
     if (!(tmin <= tmax)) return;
-    const Grid g = {a.sdf, a.scales, a.n_grid, a.nb, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e,
-                    a.slope_x, a.slope_y, a.slope_z, a.inv_hd};
+    const Grid g = grid_of(a);
     int64_t node[8];
     float dt[8];
     if (!df_hit_gradient(g, a.ox[i], a.oy[i], a.oz[i], a.dx[i], a.dy[i], a.dz[i], tmin, tmax, t_hit[i], node, dt))

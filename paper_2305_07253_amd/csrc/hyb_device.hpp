@@ -843,13 +843,13 @@ HYB_HD float cell_lipschitz(const float f[8], float inv_h) {
 // Lipschitz bound used for steps, from the largest cell bound of the grid: at
 // least 1 (keeps steps finite on flat fields), rounded up a few ulps so it
 // stays a bound after FP32 evaluation.
-inline float finish_lipschitz(float cell_max) { return fmaxf(cell_max, 1.0f) * (1.0f + 4e-7f); }
+HYB_HD float finish_lipschitz(float cell_max) { return fmaxf(cell_max, 1.0f) * (1.0f + 4e-7f); }
 
 // Per-axis slope bound from the largest cell value, rounded up likewise.
-inline float finish_slope(float cell_max) { return cell_max * (1.0f + 4e-7f); }
+HYB_HD float finish_slope(float cell_max) { return cell_max * (1.0f + 4e-7f); }
 
 // Reciprocal step factor: g * inv_step(L) is a safe sphere-tracing step.
-inline float inv_step(float lipschitz) { return (1.0f / lipschitz) * (1.0f - 1e-6f); }
+HYB_HD float inv_step(float lipschitz) { return (1.0f / lipschitz) * (1.0f - 1e-6f); }
 
 // Step slack for grids whose samples are FP32 roundings of a 1-Lipschitz
 // function f (an exact distance field).  Then |f~ - f| <= E + q with
@@ -857,7 +857,7 @@ inline float inv_step(float lipschitz) { return (1.0f / lipschitz) * (1.0f - 1e-
 // the storage error, so f~ stays positive for a distance g - 2 (E + q) ahead.
 // q covers one FP32 rounding of any sample (|f| <= the grid diagonal) plus a
 // margin of 1e-4 h.
-inline float certified_slack(float h, int n) {
+HYB_HD float certified_slack(float h, int n) {
     const float q = 1e-4f * h + 2.4e-7f * 1.7320508f * (float)(n - 1) * h;
     return 2.0f * (0.8660254f * h * (1.0f + 1e-6f) + q);
 }
@@ -904,6 +904,26 @@ HYB_HD int entry_node(const TraceArgs& a, float ox, float oy, float oz, float dx
 // nearest-first order prunes little and costs a sorting network per node).
 constexpr float kShortSegment = 4.0f;
 
+// The grid of a query's arguments, with the step bounds of a deferred
+// update read from the device (uniform loads) where the arguments point at
+// them.
+HYB_HD Grid grid_of(const TraceArgs& a) {
+    Grid g = {a.sdf, a.scales, a.n_grid, a.nb, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e,
+              a.slope_x, a.slope_y, a.slope_z, a.inv_hd};
+    if (a.bounds) {
+        g.inv_l = a.bounds[kBInvL];
+        g.slope_x = a.bounds[kBSlopeX];
+        g.slope_y = a.bounds[kBSlopeY];
+        g.slope_z = a.bounds[kBSlopeZ];
+        g.two_e = a.bounds[kBTwoE];
+    }
+    return g;
+}
+
+// A deferred update found a sample that is not finite: the distance-field
+// part of every query reports NaN (prim -2) until the next update.
+HYB_HD bool df_unusable(const TraceArgs& a) { return a.bounds && a.bounds[kBBad] != 0.0f; }
+
 // One ray of a query (the body of the trace kernels).
 template <int MODE, int FMT, bool COUNT, int LDS = kLdsDepth>
 HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
@@ -918,9 +938,11 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
     hit.u = 0.0f;
     hit.v = 0.0f;
     if (tmin <= tmax) {
-        const Grid g = {a.sdf, a.scales, a.n_grid, a.nb, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e,
-                        a.slope_x, a.slope_y, a.slope_z, a.inv_hd};
-        if (MODE == kBvhOnly) {
+        const Grid g = grid_of(a);
+        if (MODE != kBvhOnly && df_unusable(a)) {
+            hit.t = __builtin_nanf("");
+            hit.prim = -2;
+        } else if (MODE == kBvhOnly) {
             hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, tmax, stack, stride, cnt,
                                                  entry_node(a, ox, oy, oz, dx, dy, dz, tmin, tmax));
         } else if (MODE == kDfOnly) {

@@ -33,6 +33,10 @@ struct TraceArgs {
     float tmax, tau, tau_end;
     int64_t n;
     double inv_hd;  // 1 / h in FP64 (scales the distance field's FP64 ray position)
+    // Step bounds on the device (null: the fields above hold them): the grid
+    // was last updated without a wait (kDeviceBounds floats, see
+    // launch_finish_bounds)
+    const float* bounds;
 };
 
 hipError_t launch_trace(int mode, bool counters, const TraceArgs& a, hipStream_t stream);
@@ -96,6 +100,18 @@ hipError_t launch_sdf_build(const SdfBuildArgs& a, hipStream_t stream);
 // 1 if some sample of its cells is NaN or infinite else 0); returns n_blocks
 // through *n_blocks.
 constexpr int kBoundValues = 5;
+// The step bounds a deferred update leaves on the device: inv_l, slope_x,
+// slope_y, slope_z, two_e, a flag (nonzero: a sample was not finite) and the
+// Lipschitz bound itself.
+constexpr int kDeviceBounds = 8;
+enum DeviceBound : int { kBInvL = 0, kBSlopeX = 1, kBSlopeY = 2, kBSlopeZ = 3, kBTwoE = 4, kBBad = 5, kBLipschitz = 6 };
+// Reduces the n_blocks per-block maxima of launch_lipschitz into the step
+// bounds (out, kDeviceBounds floats), as the host does: pass 0 only the
+// non-finite flag (a pass over the input of a compact format, before it is
+// quantized), pass 1 all of them with the flag kept set by pass 0, pass 2 all
+// of them with a fresh flag.  two_e: the certified-grid slack, or +inf.
+hipError_t launch_finish_bounds(const float* block_max, int32_t n_blocks, int pass, float two_e, float* out,
+                                hipStream_t stream);
 hipError_t launch_lipschitz(const float* grid, int32_t n, float h, float* block_max, int32_t* n_blocks,
                             hipStream_t stream);
 int32_t lipschitz_blocks(int32_t n);

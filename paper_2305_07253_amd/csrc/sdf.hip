@@ -187,6 +187,45 @@ int32_t lipschitz_blocks(int32_t n) {
     return (int32_t)(b < 2048 ? b : 2048);
 }
 
+// The step bounds from the per-block maxima of k_lipschitz, on the device:
+// the same maxima and the same finishing as the host's (bit for bit).
+// pass 0: only the non-finite flag; 1: bounds, the flag kept set by pass 0;
+// 2: bounds and a fresh flag.
+__global__ __launch_bounds__(256) void k_finish_bounds(const float* __restrict__ block_max, int32_t n_blocks,
+                                                       int32_t pass, float two_e, float* __restrict__ out) {
+    constexpr int V = kBoundValues;
+    __shared__ float red[V][256];
+    float m[V] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int b = threadIdx.x; b < n_blocks; b += 256)
+        for (int c = 0; c < V; ++c) m[c] = fmaxf(m[c], block_max[V * b + c]);
+    for (int c = 0; c < V; ++c) red[c][threadIdx.x] = m[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int c = 0; c < V; ++c) red[c][threadIdx.x] = fmaxf(red[c][threadIdx.x], red[c][threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    bool bad = red[4][0] != 0.0f;
+    for (int c = 0; c < 4; ++c) bad = bad || !(red[c][0] <= 3.402823466e38f);
+    if (pass == 1) bad = bad || out[kBBad] != 0.0f;
+    out[kBBad] = bad ? 1.0f : 0.0f;
+    if (pass == 0) return;
+    const float L = finish_lipschitz(red[0][0]);
+    out[kBLipschitz] = L;
+    out[kBInvL] = inv_step(L);
+    out[kBSlopeX] = finish_slope(red[1][0]);
+    out[kBSlopeY] = finish_slope(red[2][0]);
+    out[kBSlopeZ] = finish_slope(red[3][0]);
+    out[kBTwoE] = two_e;
+}
+
+hipError_t launch_finish_bounds(const float* block_max, int32_t n_blocks, int pass, float two_e, float* out,
+                                hipStream_t stream) {
+    hipLaunchKernelGGL(k_finish_bounds, dim3(1), dim3(256), 0, stream, block_max, n_blocks, (int32_t)pass, two_e, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_lipschitz(const float* grid, int32_t n, float h, float* block_max, int32_t* n_blocks,
                             hipStream_t stream) {
     const int32_t b = lipschitz_blocks(n);

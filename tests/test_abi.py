@@ -49,6 +49,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.hyb_sdf_info(None, None, None, None) == 1
     h = ctypes.c_float()
     assert lib.hyb_sdf_voxel_size(None, ctypes.byref(h)) == 1
+    assert lib.hyb_sdf_check(None, None) == 1
     assert lib.hyb_bvh_destroy(None) == 1 and lib.hyb_sdf_destroy(None) == 1
     # non-finite vertex, out-of-range index, negative counts
     v = np.array([[0, 0, 0], [1, 0, 0], [0, np.nan, 0]], np.float32)

@@ -160,3 +160,89 @@ def test_batch_follows_update(hyb, tiny, grids):
             got = [x.cpu().numpy() for x in out]
             for k, (x, y) in enumerate(zip(got, ref)):
                 assert np.array_equal(x, y), (graph, k)
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("certified", [False, True])
+def test_deferred_update_equals_fresh_grid(hyb, tiny, grids, fmt, certified):
+    """An update that does not wait for the device (the bounds finished on
+    the device and read there by the kernels) gives every result, the
+    samples and the bound of a fresh grid bit for bit, over repeated updates
+    and mixed with waiting ones; the bound's readback waits for the device."""
+    g1, g2 = grids
+    sc = tiny["scene"]
+    bvh = hyb.build_bvh(sc.verts, sc.tris)
+    R = _dev(tiny["free"].soa())
+    a = hyb.sdf_from_grid(_dev(g1.reshape(-1)), tiny["grid4"], fmt=fmt)
+    g3 = g2.copy()
+    g3[0, 0, 0] = 1000.0  # an inflated bound
+    for g, deferred in ((g2, True), (g1, True), (g3, True), (g2, False), (g1, True)):
+        hyb.sdf_update(a, _dev(g.reshape(-1)), lipschitz_samples=certified, deferred=deferred)
+        b = hyb.sdf_from_grid(_dev(g.reshape(-1)), tiny["grid4"], lipschitz_samples=certified, fmt=fmt)
+        assert np.array_equal(hyb.sdf_read(a).cpu().numpy(), hyb.sdf_read(b).cpu().numpy())
+        for k, (x, y) in enumerate(zip(_all_outputs(hyb, bvh, a, R), _all_outputs(hyb, bvh, b, R))):
+            assert np.array_equal(x, y), (fmt, certified, deferred, k)
+        assert a.lipschitz == b.lipschitz
+        a.check()
+
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_deferred_update_non_finite(hyb, tiny, grids, fmt):
+    """A deferred update with a sample that is not finite: every query that
+    reads the grid reports t = NaN, prim = -2 for every ray (triangles only
+    unaffected), the backward (FP32) adds nothing, hyb_sdf_check reports it, and the
+    next good update restores exact results."""
+    import torch
+    g1, _ = grids
+    sc = tiny["scene"]
+    bvh = hyb.build_bvh(sc.verts, sc.tris)
+    R = _dev(tiny["surf"].soa())
+    a = hyb.sdf_from_grid(_dev(g1.reshape(-1)), tiny["grid4"], fmt=fmt)
+    ref = _all_outputs(hyb, bvh, a, R)
+    tri = [x.cpu().numpy() for x in hyb.trace_bvh(bvh, R, TMAX)]
+    for v in (np.nan, np.inf) + ((1e6,) if fmt == 1 else ()):
+        bad = g1.copy()
+        bad[7, 2, 30] = v
+        hyb.sdf_update(a, _dev(bad.reshape(-1)), deferred=True)
+        for tau in (0.0, 1.0):
+            t, prim, _, _ = hyb.trace(bvh, a, R, TMAX, tau)
+            assert torch.isnan(t).all() and (prim == -2).all(), (v, tau)
+        t, prim, _, _ = hyb.trace_df(a, R, TMAX)
+        assert torch.isnan(t).all() and (prim == -2).all()
+        if fmt == 0:  # the backward takes FP32 grids
+            grad = torch.zeros(g1.size, device="cuda")
+            hyb.df_backward(a, R, TMAX, t, torch.ones_like(t), grad)
+            assert not grad.any()
+        assert all(np.array_equal(x.cpu().numpy(), y) for x, y in zip(hyb.trace_bvh(bvh, R, TMAX), tri))
+        with pytest.raises(hyb.HybError):
+            a.check()
+        hyb.sdf_update(a, _dev(g1.reshape(-1)), deferred=True)
+        a.check()
+        for k, (x, y) in enumerate(zip(_all_outputs(hyb, bvh, a, R), ref)):
+            assert np.array_equal(x, y), (v, k)
+
+
+def test_batch_follows_deferred_update(hyb, tiny, grids):
+    """A batch holding a handle updated without waiting reads the bounds on
+    the device at its next launch: every result equal to hyb_trace."""
+    g1, g2 = grids
+    sc = tiny["scene"]
+    bvh = hyb.build_bvh(sc.verts, sc.tris)
+    R = _dev(tiny["surf"].soa())
+    n = R.shape[1]
+    sdf = hyb.sdf_from_grid(_dev(g1.reshape(-1)), tiny["grid4"], lipschitz_samples=True)
+    out = hyb.alloc_hits(n)
+    batch = hyb.Batch([dict(bvh=bvh, sdf=sdf, rays=R, out=out, tmax=TMAX, threshold=1.0)])
+    batch.launch()
+    g3 = g2.copy()
+    g3[0, 0, 0] = 1000.0
+    for g in (g3, g2):
+        hyb.sdf_update(sdf, _dev(g.reshape(-1)), deferred=True)
+        ref = [x.cpu().numpy() for x in hyb.trace(bvh, sdf, R, TMAX, 1.0)]
+        for graph in (False, True):
+            for x in out:
+                x.fill_(7)
+            batch.launch(graph=graph)
+            got = [x.cpu().numpy() for x in out]
+            for k, (x, y) in enumerate(zip(got, ref)):
+                assert np.array_equal(x, y), (graph, k)
