@@ -207,7 +207,9 @@ hyb_status hyb_sdf_from_grid(const float* values, int32_t n, const float* grid4,
 hyb_status hyb_sdf_update(hyb_sdf sdf, const float* values, uint32_t flags, void* stream);
 
 /* Whether the grid's last update (with HYB_SDF_UPDATE_DEFERRED) had only
- * finite samples: waits for `stream` (the update's), then HYB_OK, or
+ * finite samples, so that its interpolant, the distance field of Section 3
+ * ("Distance Field Generation"), is defined everywhere: waits for `stream`
+ * (the update's), then HYB_OK, or
  * HYB_ERR_INVALID_ARG when a sample was NaN or infinite (or, for HYB_SDF_F16,
  * beyond the half range) or for a NULL handle.  HYB_OK after any other
  * update (those check synchronously). */
