@@ -1,0 +1,40 @@
+"""The committed rocprofv3 records the benchmark line reads: the GI counter
+record was taken on the current kernel sources (else `roofline.traffic` would
+be null), holds both thresholds the line reports, and its traffic and issue
+figures are consistent with the kernel times of the same record."""
+import json
+import math
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    return bench
+
+
+def test_counter_record_matches_the_kernel_sources(bench):
+    for tau in (0.0, 1.0):
+        rec = bench.measured_counters(tau)
+        assert rec is not None, "profiles/counters_gi1080p.json was taken on other kernel sources: profile again"
+        # traffic beyond L2 within a factor of the GI query's algorithmic bytes
+        # (about 650 B/ray at threshold 0, 1.4 kB at 1, for 2,073,600 rays)
+        traffic = rec["read_bytes"] + rec["write_bytes"]
+        assert 0.5e9 < traffic < 4e9
+        issue_us = rec["valu_insts"] * 4.0 / bench.N_SIMD / bench.CLOCK_HZ * 1e6
+        assert 0.5 * rec["kernel_us"] < issue_us <= 1.05 * rec["kernel_us"]
+        assert 0.0 < rec["lane_utilisation"] <= 1.0 and 0.0 < rec["l2_hit"] <= 1.0
+
+
+def test_roofline_block_uses_the_record(bench):
+    """The roofline helper returns the record's traffic and the VALU roof."""
+    r = bench.roofline((0.0, 0.0, 18.6), 2073600, 0.34, 0.0)
+    assert r["bound"] == "alu" and r["traffic"] is not None and "issue" in r
+    assert math.isclose(r["peak"], 256 * 4 * 16 * 2.4e9 / 1e12)
+    assert math.isclose(r["frac"], r["achieved"] / r["peak"])
