@@ -587,7 +587,12 @@ def bench_precision(args, torch, hyb, W, dev, stream):
                 name, tau, ms, rays.n / ms / 1e3, same.mean(), rel.mean(), np.percentile(rel, 99)))
     return {"config": "precision", "workload": "%d-triangle room, 256^3 grid (h=1/251), %d rays (4 per pixel, "
             "1920x1080 G-buffer), tmax 0.5" % (scene.n_tris, rays.n), "oracle_sample": int(len(idx)),
-            "kernel_store_bytes": {"f32": 4 * 32 * 128 ** 3, "f16": 2 * 8 * 255 ** 3, "i8": 8 * 255 ** 3 + 4 * 32 ** 3},
+            # the bricked copies the kernels read at n = 256: FP32 and F16 in
+            # two-cell bricks of 32 slots (128^3 bricks; F16 takes them past
+            # n = 205), I8 in one-cell bricks of 8 codes + the block scale
+            # (255^3 cells of 12 B); I8 also keeps its 32^3 block scales
+            "kernel_store_bytes": {"f32": 4 * 32 * 128 ** 3, "f16": 2 * 32 * 128 ** 3, "i8": 12 * 255 ** 3},
+            "i8_scale_table_bytes": 4 * 32 ** 3,
             "linear_fp32_bytes": 4 * 256 ** 3,
             "results": res}
 

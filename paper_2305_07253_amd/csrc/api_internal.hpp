@@ -188,9 +188,7 @@ inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s
     }
     if (s) {
         a.sdf = s->store;
-        a.scales = s->scales;
         a.fmt = s->layout;
-        a.nb = s->nb;
         a.n_grid = s->n;
         a.lo_x = s->grid4[0];
         a.lo_y = s->grid4[1];

@@ -297,9 +297,8 @@ constexpr int kScaleBlock = 8;  // I8: one scale per block of 8^3 cells
 HYB_HD int i8_blocks(int n) { return (n - 1 + kScaleBlock - 1) / kScaleBlock; }
 
 struct Grid {
-    const void* __restrict__ v;        // samples in the bricked layout Brick<FMT> (float, _Float16 or int8_t)
-    const float* __restrict__ scales;  // I8: per block of cells (cell (i,j,k) -> block (i/8, j/8, k/8))
-    int n, nb;                         // samples per axis, scale blocks per axis
+    const void* __restrict__ v;  // samples in the bricked layout Brick<FMT> (float, _Float16 or int8_t)
+    int n;                       // samples per axis
     float lo_x, lo_y, lo_z, h, inv_h;
     float inv_l;    // 1 / Lipschitz bound of the interpolant (slightly reduced)
     float two_e;    // 2 x (interpolation error bound + storage error), +inf if uncertified
@@ -319,7 +318,11 @@ struct Grid {
 //   F32: C = 2, the 27 samples of a brick padded to 32 (4x the n^3 samples):
 //        each brick is one 128-byte cache line, so a fetch touches exactly one
 //        (unpadded, 43% of the 56-byte fetches straddled two)
-//   F16, I8: C = 1, the 8 corners of each cell contiguous (16 / 8 B, one load)
+//   F16: C = 1, the 8 corners of each cell contiguous (16 B, one load)
+//   I8: C = 1, the 8 codes of each cell, then the scale of the cell's block
+//        (a float in slots 8-11): 12 B, one load per fetch with no table
+//        lookup; the block's scale repeats in each of its cells (1.5x the
+//        bytes of codes alone, three quarters of one-cell F16)
 //   F16 of large grids (kF16B2): C = 2, 27 halves padded to 32 (64 B): half
 //        the footprint of one-cell bricks, eight 2-byte loads per fetch
 // Slots of nodes beyond the grid are padding and never read.
@@ -328,7 +331,8 @@ struct Brick {
     static constexpr int kCells = FMT == kF32 || FMT == kF16B2 ? 2 : 1;
     static constexpr int kSide = kCells + 1;
     static constexpr int kNodes = kSide * kSide * kSide;
-    static constexpr int kStride = kCells == 2 ? 32 : kNodes;  // slots per brick (padding at the end)
+    // slots per brick: padding at the end (two-cell bricks), the scale (I8)
+    static constexpr int kStride = kCells == 2 ? 32 : (FMT == kI8 ? kNodes + 4 : kNodes);
 
     HYB_HD static int per_axis(int n) { return (n - 1 + kCells - 1) / kCells; }
 
@@ -389,7 +393,7 @@ inline int f16_layout(int n) {
 
 // The 8 samples of cell (i, j, k), corner c = (i + (c & 1), j + (c >> 1 & 1), k + (c >> 2)).
 template <int FMT>
-HYB_HD void corners(const Grid& g, int i, int j, int k, float f[8]) {
+HYB_HD float corners(const Grid& g, int i, int j, int k, float f[8]) {
     using B = Brick<FMT>;
     constexpr int S = B::kSide, S2 = B::kSide * B::kSide;
     constexpr int off[8] = {0, 1, S, S + 1, S2, S2 + 1, S2 + S, S2 + S + 1};
@@ -397,20 +401,22 @@ HYB_HD void corners(const Grid& g, int i, int j, int k, float f[8]) {
     if constexpr (FMT == kF32) {
         const float* p = static_cast<const float*>(g.v) + slot;
         for (int c = 0; c < 8; ++c) f[c] = p[off[c]];
+        return 1.0f;
     } else if constexpr (FMT == kF16 || FMT == kF16B2) {
         const _Float16* p = static_cast<const _Float16*>(g.v) + slot;
         for (int c = 0; c < 8; ++c) f[c] = (float)p[off[c]];
+        return 1.0f;
     } else {
-        // the 8 codes are multiples of the one scale of the cell's block
-        // (exact products: the scales are powers of two).  The table has at
-        // most 128^3 entries, so its byte offset is 32-bit, formed with 24-bit
-        // multiply-adds.
-        const int8_t* p = static_cast<const int8_t*>(g.v) + slot;
-        const uint32_t nb4 = 4u * (uint32_t)g.nb, nbb4 = nb4 * (uint32_t)g.nb;
-        const uint32_t bi = (uint32_t)i / kScaleBlock, bj = (uint32_t)j / kScaleBlock, bk = (uint32_t)k / kScaleBlock;
-        const float s = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(g.scales) +
-                                                        mad24(bk, nbb4, mad24(bj, nb4, 4u * bi)));
-        for (int c = 0; c < 8; ++c) f[c] = (float)p[off[c]] * s;
+        // the 8 codes are multiples of the scale stored after them, the one
+        // scale of the cell's block (exact products: the scales are powers of
+        // two); the 12 bytes are 4-aligned (slot = 12 x brick)
+        struct alignas(4) Cell {
+            int8_t q[8];
+            float s;
+        };
+        const Cell c8 = *reinterpret_cast<const Cell*>(static_cast<const int8_t*>(g.v) + slot);
+        for (int c = 0; c < 8; ++c) f[c] = (float)c8.q[off[c]];
+        return c8.s;
     }
 }
 
@@ -648,16 +654,16 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     const int nm2 = g.n - 2;
     const double X = fma((double)r.t, r.qx, r.px), Y = fma((double)r.t, r.qy, r.py), Z = fma((double)r.t, r.qz, r.pz);
     if (!r.walk) {
-        r.ci = min(max((int)floor(X), 0), nm2);
-        r.cj = min(max((int)floor(Y), 0), nm2);
-        r.ck = min(max((int)floor(Z), 0), nm2);
+        r.ci = min(max((int)X, 0), nm2);
+        r.cj = min(max((int)Y, 0), nm2);
+        r.ck = min(max((int)Z, 0), nm2);
     }
     const float fx = (float)(X - r.ci), fy = (float)(Y - r.cj), fz = (float)(Z - r.ck);
     float f[8];
-    corners<FMT>(g, r.ci, r.cj, r.ck, f);
+    const float s = corners<FMT>(g, r.ci, r.cj, r.ck, f);
     if (COUNT) cnt.df++;
     const CellLerp L = lerp_cell(f, fx, fy, fz);
-    const float val = L.val;
+    const float val = L.val * s;
     // no root within `safe` of this point (0 at or below the surface)
     const float safe = val > 0.0f ? fmaxf(val * r.inv_l, val - g.two_e) : 0.0f;
     if (r.t - safe > r.cover) {
@@ -697,6 +703,7 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     if (min_bits(f) <= 0) {
         // some corner at or below zero: the cell's cubic along the ray
         cell_cubic(L, fy, fz, r.qxf, r.qyf, r.qzf, r.k);
+        for (int m = 0; m < 4; ++m) r.k[m] *= s;
         r.span = fminf(t_exit, r.b) - r.t;
         if (cubic_may_vanish(r.k, r.span)) {
             r.t_exit = t_exit;
@@ -796,7 +803,7 @@ HYB_HD bool df_hit_gradient(const Grid& g, float ox, float oy, float oz, float d
     if (!df_init(g, ox, oy, oz, dx, dy, dz, a, b, r) || !(t_hit > r.t)) return false;
     const int nm2 = g.n - 2;
     const double X = fma((double)t_hit, r.qx, r.px), Y = fma((double)t_hit, r.qy, r.py), Z = fma((double)t_hit, r.qz, r.pz);
-    const int ci = min(max((int)floor(X), 0), nm2), cj = min(max((int)floor(Y), 0), nm2), ck = min(max((int)floor(Z), 0), nm2);
+    const int ci = min(max((int)X, 0), nm2), cj = min(max((int)Y, 0), nm2), ck = min(max((int)Z, 0), nm2);
     const float fx = (float)(X - ci), fy = (float)(Y - cj), fz = (float)(Z - ck);
     float f[8];
     corners<kF32>(g, ci, cj, ck, f);
@@ -908,7 +915,7 @@ constexpr float kShortSegment = 4.0f;
 // update read from the device (uniform loads) where the arguments point at
 // them.
 HYB_HD Grid grid_of(const TraceArgs& a) {
-    Grid g = {a.sdf, a.scales, a.n_grid, a.nb, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e,
+    Grid g = {a.sdf, a.n_grid, a.lo_x, a.lo_y, a.lo_z, a.h, a.inv_h, a.inv_l, a.two_e,
               a.slope_x, a.slope_y, a.slope_z, a.inv_hd};
     if (a.bounds) {
         g.inv_l = a.bounds[kBInvL];

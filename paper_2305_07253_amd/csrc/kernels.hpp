@@ -22,10 +22,9 @@ struct TraceArgs {
     const int32_t* entry;  // traversal entry pyramid (null: start at the root)
     float entry_lo_x, entry_lo_y, entry_lo_z, entry_inv;  // origin, 1 / finest voxel side
     int32_t entry_res, entry_levels;
-    const void* sdf;      // samples in the grid's storage format
-    const float* scales;  // I8 block scales or null
-    int32_t fmt;          // SdfFormat
-    int32_t n_grid, nb;
+    const void* sdf;  // samples in the grid's storage format
+    int32_t fmt;      // SdfFormat
+    int32_t n_grid;
     float lo_x, lo_y, lo_z, h, inv_h, inv_l;
     float two_e;  // certified-grid step slack (+inf: use g / L only)
     float slope_x, slope_y, slope_z;  // per-axis bounds of the interpolant's partial derivatives
@@ -73,8 +72,12 @@ hipError_t launch_count_mismatch(const float* t, const int32_t* prim, const floa
 // the node Brick<fmt>::slot_node(s)), in the storage format:
 //   F32: the value
 //   F16: round-to-nearest-even half of the value
-//   I8:  scales[b] = max |value| over the nodes of 8^3 block b / 127 (1 if that
-//        is 0), q = rint(value / scale of its block) clamped to [-127, 127]
+//   I8:  scales[b] = the smallest power of two 2^e (e >= -126) with
+//        127 * 2^e >= max |value| over the nodes of 8^3 block b; a node's
+//        value becomes q * S, S the largest scale of the blocks holding it and
+//        q = rint(value / S) clamped to +-floor(127 * smallest / S), an integer
+//        multiple of every holding block's scale; each cell stores the codes of
+//        its 8 corners for its own block's scale, then that scale
 // For F16 / I8, `values` is then overwritten in place by the dequantized FP32
 // values (what the trace kernels interpolate).
 hipError_t launch_quantize(int fmt, float* values, int32_t n, void* out, float* scales, hipStream_t stream);

@@ -92,15 +92,18 @@ __device__ void store_slot(const float* __restrict__ in, int32_t n, int32_t nb, 
     } else {
         // `in` holds the dequantized values: a node's value is an integer
         // multiple of the scale of every block holding it, here the block of
-        // the slot's cell (one-cell bricks: brick = cell)
-        float q = 0.0f;
-        if (node) {
-            const int64_t b = s / Brick<kI8>::kStride;
-            const int nc = Brick<kI8>::per_axis(n);
-            const int ci = (int)(b % nc), cj = (int)((b / nc) % nc), ck = (int)(b / ((int64_t)nc * nc));
-            q = f / scales[ci / kScaleBlock + nb * (cj / kScaleBlock + nb * (ck / kScaleBlock))];
-        }
-        static_cast<int8_t*>(out)[s] = (int8_t)q;
+        // the slot's cell (one-cell bricks: brick = cell); slots 8-11 of the
+        // cell hold the bytes of that scale
+        using B = Brick<kI8>;
+        const int64_t b = s / B::kStride;
+        const int r = (int)(s - b * B::kStride);
+        const int nc = B::per_axis(n);
+        const int ci = (int)(b % nc), cj = (int)((b / nc) % nc), ck = (int)(b / ((int64_t)nc * nc));
+        const float sc = scales[ci / kScaleBlock + nb * (cj / kScaleBlock + nb * (ck / kScaleBlock))];
+        uint8_t byte;
+        if (r >= B::kNodes) byte = (uint8_t)(__builtin_bit_cast(uint32_t, sc) >> (8 * (r - B::kNodes)));
+        else byte = node ? (uint8_t)(int8_t)(f / sc) : 0;
+        static_cast<uint8_t*>(out)[s] = byte;
     }
 }
 

@@ -13,8 +13,8 @@
 //           f16 values [N^3] for fmt 1 and 3 (fmt 3: laid out in the two-cell
 //           bricks of large grids), the f32 block scales [nb^3] (blocks of 8^3
 //           cells) for fmt 2, all x fastest (the emulator lays them out in
-//           bricks; I8 codes are the dequantized values over the scale of
-//           the cell's block),
+//           bricks; an I8 cell holds its corners' dequantized values over
+//           the scale of its block, then that scale),
 //         rays f32[6 n_rays] (SoA rows), tmin f32[n_rays], tmax f32[n_rays]
 // what 0 (trace): output t f32[n], prim i32[n], u f32[n], v f32[n], counts i32[3n]
 // what 1 (sdf):   output f32[N^3] signed distances of the grid nodes
@@ -25,6 +25,7 @@
 //                 f32[8] d t / d sample
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "bvh_build.hpp"
@@ -132,15 +133,21 @@ int main(int argc, char** argv) {
         if (fmt == 3 ? hyb::Brick<hyb::kF16B2>::slot_node((int64_t)s, (int)N, i, j, k)
                      : hyb::Brick<hyb::kF16>::slot_node((int64_t)s, (int)N, i, j, k))
             b16[s] = g16.at(i + N * (j + N * (long long)k));
-    for (size_t s = 0; s < b8.size(); ++s)
-        if (hyb::Brick<hyb::kI8>::slot_node((int64_t)s, (int)N, i, j, k)) {
-            const long long b = (long long)s / hyb::Brick<hyb::kI8>::kStride, nc = N - 1;
-            const long long ci = b % nc, cj = (b / nc) % nc, ck = b / (nc * nc);
-            const float sc = scales.at(ci / 8 + nb * (cj / 8 + nb * (ck / 8)));
+    for (size_t s = 0; s < b8.size(); ++s) {
+        const long long b = (long long)s / hyb::Brick<hyb::kI8>::kStride, nc = N - 1;
+        const int r = (int)((long long)s - b * hyb::Brick<hyb::kI8>::kStride);
+        const long long ci = b % nc, cj = (b / nc) % nc, ck = b / (nc * nc);
+        const float sc = scales.at(ci / 8 + nb * (cj / 8 + nb * (ck / 8)));
+        if (r >= hyb::Brick<hyb::kI8>::kNodes) {  // the cell's scale after its codes
+            uint32_t bits;
+            std::memcpy(&bits, &sc, 4);
+            b8[s] = (int8_t)(uint8_t)(bits >> (8 * (r - hyb::Brick<hyb::kI8>::kNodes)));
+        } else if (hyb::Brick<hyb::kI8>::slot_node((int64_t)s, (int)N, i, j, k)) {
             const float q = grid.at(i + N * (j + N * (long long)k)) / sc;
             if (!(q == (float)(int)q && q >= -127.0f && q <= 127.0f)) return 5;  // not a code of this block
             b8[s] = (int8_t)q;
         }
+    }
 
     std::vector<float> t(n), u(n), v(n);
     std::vector<int32_t> prim(n), counts(3 * n);
@@ -163,9 +170,7 @@ int main(int argc, char** argv) {
     a.sdf = grid.empty() ? nullptr
             : (fmt == 1 || fmt == 3 ? static_cast<const void*>(b16.data())
                         : (fmt == 2 ? static_cast<const void*>(b8.data()) : static_cast<const void*>(b32.data())));
-    a.scales = scales.empty() ? nullptr : scales.data();
     a.fmt = fmt;
-    a.nb = (int)nb;
     a.n_grid = (int)N;
     a.lo_x = par[2]; a.lo_y = par[3]; a.lo_z = par[4]; a.h = par[5]; a.inv_h = inv_h; a.inv_hd = 1.0 / (double)par[5];
     a.inv_l = hyb::inv_step(L);
@@ -177,7 +182,7 @@ int main(int argc, char** argv) {
     a.tau = par[1];
     a.n = n;
     if (what == 2) {
-        const hyb::Grid g = {b32.data(), nullptr, (int)N, 0, par[2], par[3], par[4], par[5], inv_h, a.inv_l,
+        const hyb::Grid g = {b32.data(), (int)N, par[2], par[3], par[4], par[5], inv_h, a.inv_l,
                              __builtin_inff(), a.slope_x, a.slope_y, a.slope_z, 1.0 / (double)par[5]};
         std::vector<long long> nodes(8 * n, -1);
         std::vector<float> dts(8 * n, 0.0f);
