@@ -402,7 +402,7 @@ hyb_status hyb_batch_destroy(hyb_batch batch);
  * own threshold and no tuning) whose work counter, item offsets and
  * descriptor table live in a fixed device array of the library instead of
  * memory a batch allocates.  The array holds up to HYB_STATIC_BATCH_MAX_ITEMS
- * items (62,976 bytes, one copy per device, kept until the process ends; its
+ * items (65,024 bytes, one copy per device, kept until the process ends; its
  * address is looked up on the first call on each device).  Nothing is
  * allocated, on the device or the host; the descriptors are written by small
  * fill kernels whose arguments carry them, so `items` may be reused on
