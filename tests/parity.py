@@ -144,3 +144,16 @@ def combined_oracle(orc, verts, tris, grids, g4, rays_soa, tmax, tau):
         c = np.where(hit, ct, cd)
         out.append((ref, m, c))
     return out
+
+
+def lossless_grid(grid):
+    """The grid rounded to integer multiples q s of one power of two s with
+    |q| <= 127 (s the smallest with 127 s >= max |grid|): F16 holds every
+    such value exactly, and so does I8, whose scale of any block is a power
+    of two dividing s (codes q s / scale stay within 127, also on the faces
+    blocks share), so all formats store the same samples."""
+    g = np.asarray(grid, np.float32)
+    m = float(np.abs(g).max())
+    s = 2.0 ** int(np.ceil(np.log2(m / 127.0))) if m > 0 else 1.0
+    q = np.clip(np.rint(g.astype(np.float64) / s), -127, 127)
+    return (q * s).astype(np.float32)

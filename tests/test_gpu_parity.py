@@ -338,6 +338,29 @@ def test_gi_formats_full_launch(hyb, orc, gi, fmt):
         parity.check(got, ref, m, c, label="gi fmt %d tau %s" % (fmt, tau))
 
 
+@pytest.mark.parametrize("tau", [0.0, 1.0])
+def test_formats_agree_on_a_lossless_grid(hyb, orc, tiny, tiny_dev, gi, tau):
+    """Samples every format stores exactly (integer multiples of one power of
+    two, at most 127 of them): the F16 and I8 kernels return the FP32
+    kernel's hits bit for bit, on the tiny room and on all 2,073,600 GI rays
+    with a lossless copy of the 128^3 grid."""
+    cases = [(tiny_dev["bvh"], tiny["grid"], tiny["grid4"], tiny_dev["free"], 2.0),
+             (tiny_dev["bvh"], tiny["grid"], tiny["grid4"], tiny_dev["surf"], 2.0),
+             (gi["bvh"], gi["oracle_grid"], gi["g4"], gi["dev"], 0.5)]
+    for bvh, grid, g4, rays, tmax in cases:
+        g = parity.lossless_grid(grid)
+        for fmt in (1, 2):
+            deq, _, _ = orc.quantize(g, fmt)
+            assert np.array_equal(deq, g)
+        ref = host(hyb.trace(bvh, hyb.sdf_from_grid(to_dev(g.reshape(-1)), g4), rays, tmax, tau))
+        assert (ref[1] == -2).sum() > 100
+        for fmt in (1, 2):
+            sdf = hyb.sdf_from_grid(to_dev(g.reshape(-1)), g4, fmt=fmt)
+            got = host(hyb.trace(bvh, sdf, rays, tmax, tau))
+            for a, b in zip(got, ref):
+                assert np.array_equal(a, b), (fmt, tau, len(a))
+
+
 # ---------------------------------------------------------------------------
 # shadow-ray query: triangles at both ends, the distance field in between, any hit
 # ---------------------------------------------------------------------------

@@ -45,6 +45,26 @@ def test_compact_formats_match_oracle(emu, orc, tiny, fmt, tau):
         parity.check(got, ref, m, c, label="emu fmt %d tau %s" % (fmt, tau))
 
 
+@pytest.mark.parametrize("tau", [0.0, 1.0])
+def test_formats_agree_on_a_lossless_grid(emu, orc, tiny, tau):
+    """On samples every format stores exactly, the F16 (one- and two-cell
+    bricks) and I8 kernel bodies return the FP32 body's hits bit for bit:
+    their decoding, the I8 scale applied after interpolating the codes and
+    the brick layouts change no value the march computes."""
+    sc, g4 = tiny["scene"], tiny["grid4"]
+    g = parity.lossless_grid(tiny["grid"])
+    for fmt in (1, 2):
+        deq, _, _ = orc.quantize(g, fmt)
+        assert np.array_equal(deq, g)
+    for rays in (tiny["free"], tiny["surf"]):
+        ref = emu.trace(sc.verts, sc.tris, g, g4, rays.soa(), 2.0, tau)
+        assert (ref[1] == -2).sum() > 100  # the distance field decides many rays
+        for fmt in (1, 2, 3):
+            got = emu.trace(sc.verts, sc.tris, g, g4, rays.soa(), 2.0, tau, fmt=fmt)
+            for a, b in zip(got[:4], ref[:4]):
+                assert np.array_equal(a, b), (fmt, tau)
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_pure_modes_match_oracle(emu, orc, tiny, mode):
     sc, grid, g4 = tiny["scene"], tiny["grid"], tiny["grid4"]
