@@ -105,6 +105,7 @@ constexpr size_t kStaticTableOff = 1536;
 constexpr size_t kStaticBytes = kStaticTableOff + sizeof(TraceArgs) * kStaticItems;
 static_assert(kStaticStartOff + sizeof(uint32_t) * (kStaticItems + 1) <= kStaticTableOff, "offsets overlap");
 static_assert(sizeof(TraceArgs) % sizeof(uint32_t) == 0 && alignof(TraceArgs) <= 256, "table layout");
+static_assert(kStaticBytes == 65024, "the array size hyb_batch_launch_static documents");
 static __device__ __align__(256) unsigned char scratch[kStaticBytes];
 
 // Words of host data carried by value in one kernel's arguments (kept under

@@ -391,7 +391,10 @@ inline int f16_layout(int n) {
     return c * c * c * 16 > (int64_t(128) << 20) ? kF16B2 : kF16;
 }
 
-// The 8 samples of cell (i, j, k), corner c = (i + (c & 1), j + (c >> 1 & 1), k + (c >> 2)).
+// The 8 samples of cell (i, j, k), corner c = (i + (c & 1), j + (c >> 1 & 1), k + (c >> 2)),
+// as f[c] times the returned factor: 1, except for I8 (f the integer codes,
+// the factor their block's scale, which the caller applies after
+// interpolating: a power of two, it changes no rounding in between).
 template <int FMT>
 HYB_HD float corners(const Grid& g, int i, int j, int k, float f[8]) {
     using B = Brick<FMT>;
@@ -407,14 +410,14 @@ HYB_HD float corners(const Grid& g, int i, int j, int k, float f[8]) {
         for (int c = 0; c < 8; ++c) f[c] = (float)p[off[c]];
         return 1.0f;
     } else {
-        // the 8 codes are multiples of the scale stored after them, the one
-        // scale of the cell's block (exact products: the scales are powers of
-        // two); the 12 bytes are 4-aligned (slot = 12 x brick)
-        struct alignas(4) Cell {
+        // the 8 codes, then the scale of the cell's block: 12 bytes at a
+        // 4-aligned address (slot = 12 x brick), one load
+        struct Cell {
             int8_t q[8];
             float s;
         };
-        const Cell c8 = *reinterpret_cast<const Cell*>(static_cast<const int8_t*>(g.v) + slot);
+        Cell c8;
+        __builtin_memcpy(&c8, __builtin_assume_aligned(static_cast<const int8_t*>(g.v) + slot, 4), sizeof(Cell));
         for (int c = 0; c < 8; ++c) f[c] = (float)c8.q[off[c]];
         return c8.s;
     }

@@ -11,9 +11,9 @@
 namespace hyb {
 
 // Wavefronts per SIMD the compiler is held to where that measured faster:
-// one-cell F16 bricks, 74 VGPRs left alone, fit seven at 72; the combined I8
-// query, 82, fits six at 80 (7% faster at threshold 1; the DF-only I8 kernel
-// held to 72 was 18% slower).
+// one-cell F16 bricks, 74 VGPRs left alone, fit seven at 72.  The combined I8
+// query (77 VGPRs) is held to six: at seven it spills the walk's step, which
+// the cell steps then reload, and measured slower.
 template <int MODE, int FMT, bool COUNT>
 constexpr int trace_waves() {
     if (COUNT) return 1;
