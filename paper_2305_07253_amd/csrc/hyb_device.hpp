@@ -667,8 +667,9 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     if (COUNT) cnt.df++;
     const CellLerp L = lerp_cell(f, fx, fy, fz);
     const float val = L.val * s;
-    // no root within `safe` of this point (0 at or below the surface)
-    const float safe = val > 0.0f ? fmaxf(val * r.inv_l, val - g.two_e) : 0.0f;
+    // no root within `safe` of this point (0 at or below the surface: both
+    // bounds are then <= 0)
+    const float safe = fmaxf(fmaxf(val * r.inv_l, val - g.two_e), 0.0f);
     if (r.t - safe > r.cover) {
         // an over-relaxed step left (cover, t - safe) unchecked: go back
         r.t = r.cover;
