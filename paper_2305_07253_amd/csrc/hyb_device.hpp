@@ -649,6 +649,19 @@ HYB_HD int min_bits(const float f[8]) {
     return m;
 }
 
+HYB_HD float exit_span_of(float ex, float ey, float ez) { return fmaxf(fminf(fminf(ex, ey), ez), 0.0f); }
+
+HYB_HD int exit_axis_of(float ex, float ey, float ez) { return (ex <= ey && ex <= ez) ? 0 : (ey <= ez ? 1 : 2); }
+
+// The cubic k of the interpolant along the ray from r.t inside the cell
+// (the lerp of its samples f, times their factor s, see corners), and the
+// length of the span it covers, up to the cell's exit or the segment end.
+HYB_HD float span_cubic(const CellLerp& L, float s, float fy, float fz, const DfRay& r, float t_exit, float k[4]) {
+    cell_cubic(L, fy, fz, r.qxf, r.qyf, r.qzf, k);
+    for (int m = 0; m < 4; ++m) k[m] *= s;
+    return fminf(t_exit, r.b) - r.t;
+}
+
 // One iteration of the march: fetch the 8 corners of one cell, then either a
 // sphere step or a cell step (see df_first_root).  On kDfHit the hit is r.t;
 // kDfSolve leaves a cell span that may hold the first root for df_resolve.
@@ -682,7 +695,7 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     const float ex = fmaf(fx, r.mx, r.ex);
     const float ey = fmaf(fy, r.my, r.ey);
     const float ez = fmaf(fz, r.mz, r.ez);
-    const float exit_span = fmaxf(fminf(fminf(ex, ey), ez), 0.0f);
+    const float exit_span = exit_span_of(ex, ey, ez);
     // A sphere step far from the surface, unless it would be shorter than half
     // a cell (on a grid whose bound L is inflated, one extreme sample anywhere
     // makes every step short, and the exact cell step is longer; for any grid
@@ -703,12 +716,10 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     }
     r.walk = true;
     const float t_exit = r.t + exit_span;
-    const int axis = (ex <= ey && ex <= ez) ? 0 : (ey <= ez ? 1 : 2);
+    const int axis = exit_axis_of(ex, ey, ez);
     if (min_bits(f) <= 0) {
         // some corner at or below zero: the cell's cubic along the ray
-        cell_cubic(L, fy, fz, r.qxf, r.qyf, r.qzf, r.k);
-        for (int m = 0; m < 4; ++m) r.k[m] *= s;
-        r.span = fminf(t_exit, r.b) - r.t;
+        r.span = span_cubic(L, s, fy, fz, r, t_exit, r.k);
         if (cubic_may_vanish(r.k, r.span)) {
             r.t_exit = t_exit;
             r.axis = axis;
@@ -718,9 +729,36 @@ HYB_HD int df_step(const Grid& g, DfRay& r, Counters& cnt) {
     return df_advance(g, r, axis, t_exit);
 }
 
-// Finishes a kDfSolve: the exact first root of the cell's cubic, else on to
-// the next cell.
+// Finishes a kDfSolve: the exact first root of the cell's cubic on its span,
+// else on to the next cell.
+//
+// REFORM: the span's cubic, its end and exit face are formed here again from
+// r.t and the cell (df_step changed neither) by the functions df_step used
+// (the F32 / I8 agreement on samples every format stores exactly checks that
+// they give the same numbers); df_step's own copies are then never read, and
+// the march no longer holds them.  A lane that stops for a
+// solve keeps those seven values in registers while the rest of its
+// wavefront marches on; formed again, they cost one more fetch of the cell
+// once the wavefront's march has ended, by when its lines may have left the
+// caches.  The combined I8 kernel then fits seven wavefronts per SIMD
+// instead of six (3-4% faster at threshold 1); kernels that already fit
+// seven or more lost more to the fetch than they gained.
+template <int FMT, bool REFORM>
 HYB_HD int df_resolve(const Grid& g, DfRay& r) {
+    if constexpr (REFORM) {
+        const double X = fma((double)r.t, r.qx, r.px), Y = fma((double)r.t, r.qy, r.py),
+                     Z = fma((double)r.t, r.qz, r.pz);
+        const float fx = (float)(X - r.ci), fy = (float)(Y - r.cj), fz = (float)(Z - r.ck);
+        float f[8];
+        const float s = corners<FMT>(g, r.ci, r.cj, r.ck, f);
+        const CellLerp L = lerp_cell(f, fx, fy, fz);
+        const float ex = fmaf(fx, r.mx, r.ex);
+        const float ey = fmaf(fy, r.my, r.ey);
+        const float ez = fmaf(fz, r.mz, r.ez);
+        r.t_exit = r.t + exit_span_of(ex, ey, ez);
+        r.axis = exit_axis_of(ex, ey, ez);
+        r.span = span_cubic(L, s, fy, fz, r, r.t_exit, r.k);
+    }
     const float s = cubic_first_root(r.k, r.span);
     if (s >= 0.0f) {
         r.t += s;
@@ -765,7 +803,7 @@ HYB_HD int df_max_walk(const Grid& g) { return 3 * g.n; }
 // FP64 (on MI355X an FP64 FMA issues at the rate of an unpacked FP32 one) so
 // the in-cell fraction keeps full FP32 precision tens of cells from the
 // origin.
-template <int FMT, bool COUNT>
+template <int FMT, bool COUNT, bool REFORM = false>
 HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz, float a,
                            float b, Counters& cnt) {
     DfRay r;
@@ -777,7 +815,7 @@ HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx
     for (;;) {
         int st = kDfContinue;
         for (; budget > 0 && st == kDfContinue; --budget) st = df_step<FMT, COUNT>(g, r, cnt);
-        if (st == kDfSolve) st = df_resolve(g, r);
+        if (st == kDfSolve) st = df_resolve<FMT, REFORM>(g, r);
         if (st == kDfHit) return r.t;
         if (st == kDfMiss) return __builtin_inff();
         if (budget <= 0) {
@@ -992,7 +1030,7 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
                                                      cnt, entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1),
                                                      !(a.tau <= kShortSegment));
             if (hit.prim < 0 && (t1 < tmax || a.tau == 0.0f)) {
-                const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, tmax, cnt);
+                const float t = df_first_root<FMT, COUNT, FMT == kI8>(g, ox, oy, oz, dx, dy, dz, t1, tmax, cnt);
                 if (t != __builtin_inff()) {  // NaN: see df_first_root
                     hit.t = t;
                     hit.prim = -2;

@@ -11,14 +11,13 @@
 namespace hyb {
 
 // Wavefronts per SIMD the compiler is held to where that measured faster:
-// one-cell F16 bricks, 74 VGPRs left alone, fit seven at 72.  The combined I8
-// query (77 VGPRs) is held to six: at seven it spills the walk's step, which
-// the cell steps then reload, and measured slower.
+// one-cell F16 bricks, 74 VGPRs left alone, fit seven at 72; the combined I8
+// query, which forms its solves again (df_resolve) to fit, seven at 70.
 template <int MODE, int FMT, bool COUNT>
 constexpr int trace_waves() {
     if (COUNT) return 1;
     if (FMT == kF16 && (MODE == kCombined || MODE == kDfOnly)) return 7;
-    if (FMT == kI8 && MODE == kCombined) return 6;
+    if (FMT == kI8 && MODE == kCombined) return 7;
     return 1;
 }
 
