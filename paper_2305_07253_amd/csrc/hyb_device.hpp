@@ -143,6 +143,14 @@ HYB_HD float safe_inv(float d) {
     return 1.0f / (fabsf(d) > 1e-30f ? d : copysignf(1e-30f, d));
 }
 
+// 1 / d per component, formed once per ray for the slab tests of both
+// techniques (the BVH's boxes, the distance field's grid box).
+struct RayInv {
+    float x, y, z;
+};
+
+HYB_HD RayInv ray_inv(float dx, float dy, float dz) { return {safe_inv(dx), safe_inv(dy), safe_inv(dz)}; }
+
 // Conservative slab test: tn/tf of the box clipped to [lo, hi]; hit iff tn <= tf.
 HYB_HD void box_clip(const BoxRay& r, float lx, float hx, float ly, float hy, float lz, float hz,
                                          float seg_lo, float seg_hi, float& tn, float& tf) {
@@ -184,7 +192,7 @@ HYB_HD void order2(float& ka, int& ra, float& kb, int& rb) {
 // LDS go to a private spill area.
 template <bool COUNT, bool ANY = false, int LDS = kLdsDepth>
 HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris,
-                       float ox, float oy, float oz, float dx, float dy, float dz,
+                       float ox, float oy, float oz, float dx, float dy, float dz, const RayInv& inv,
                        float seg_lo, float seg_hi, int* stack, int stride, Counters& cnt, int start = 0,
                        bool sort = true) {
     Hit best;
@@ -192,7 +200,7 @@ HYB_HD Hit bvh_closest(const float4* __restrict__ nodes, const float4* __restric
     best.prim = -1;
     best.u = 0.0f;
     best.v = 0.0f;
-    const BoxRay br = {ox, oy, oz, safe_inv(dx), safe_inv(dy), safe_inv(dz)};
+    const BoxRay br = {ox, oy, oz, inv.x, inv.y, inv.z};
     const ShearRay sr = make_shear(dx, dy, dz);
     static_assert(LDS > 0 && LDS < kStackDepth, "LDS part of the stack out of range");
     int spill[kStackDepth - LDS];
@@ -586,10 +594,10 @@ HYB_HD int df_advance(const Grid& g, DfRay& r, int axis, float t_exit) {
 
 // Clips [a, b] to the grid box and prepares the marching state; false when the
 // segment misses the box.
-HYB_HD bool df_init(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz, float a, float b,
-                    DfRay& r) {
+HYB_HD bool df_init(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz, const RayInv& inv,
+                    float a, float b, DfRay& r) {
     const float ext = (float)(g.n - 1) * g.h;
-    const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+    const float ix = inv.x, iy = inv.y, iz = inv.z;
     const float t0x = (g.lo_x - ox) * ix, t1x = (g.lo_x + ext - ox) * ix;
     const float t0y = (g.lo_y - oy) * iy, t1y = (g.lo_y + ext - oy) * iy;
     const float t0z = (g.lo_z - oz) * iz, t1z = (g.lo_z + ext - oz) * iz;
@@ -804,10 +812,10 @@ HYB_HD int df_max_walk(const Grid& g) { return 3 * g.n; }
 // the in-cell fraction keeps full FP32 precision tens of cells from the
 // origin.
 template <int FMT, bool COUNT, bool REFORM = false>
-HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz, float a,
-                           float b, Counters& cnt) {
+HYB_HD float df_first_root(const Grid& g, float ox, float oy, float oz, float dx, float dy, float dz,
+                           const RayInv& inv, float a, float b, Counters& cnt) {
     DfRay r;
-    if (!df_init(g, ox, oy, oz, dx, dy, dz, a, b, r)) return __builtin_inff();
+    if (!df_init(g, ox, oy, oz, dx, dy, dz, inv, a, b, r)) return __builtin_inff();
     // The cubic solve runs outside the marching loop: a lane leaves the loop
     // at a cell that may hold its root and the wavefront solves all such lanes
     // together (nearly every solve ends its ray).
@@ -842,7 +850,7 @@ HYB_HD bool df_hit_gradient(const Grid& g, float ox, float oy, float oz, float d
                             float b, float t_hit, int64_t node[8], float dt[8]) {
     if (!(t_hit < __builtin_inff())) return false;
     DfRay r;
-    if (!df_init(g, ox, oy, oz, dx, dy, dz, a, b, r) || !(t_hit > r.t)) return false;
+    if (!df_init(g, ox, oy, oz, dx, dy, dz, ray_inv(dx, dy, dz), a, b, r) || !(t_hit > r.t)) return false;
     const int nm2 = g.n - 2;
     const double X = fma((double)t_hit, r.qx, r.px), Y = fma((double)t_hit, r.qy, r.py), Z = fma((double)t_hit, r.qz, r.pz);
     const int ci = min(max((int)X, 0), nm2), cj = min(max((int)Y, 0), nm2), ck = min(max((int)Z, 0), nm2);
@@ -992,10 +1000,11 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
             hit.t = __builtin_nanf("");
             hit.prim = -2;
         } else if (MODE == kBvhOnly) {
-            hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, tmax, stack, stride, cnt,
+            hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, ray_inv(dx, dy, dz), tmin,
+                                                 tmax, stack, stride, cnt,
                                                  entry_node(a, ox, oy, oz, dx, dy, dz, tmin, tmax));
         } else if (MODE == kDfOnly) {
-            const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, tmin, tmax, cnt);
+            const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, ray_inv(dx, dy, dz), tmin, tmax, cnt);
             if (t != __builtin_inff()) {  // NaN: see df_first_root
                 hit.t = t;
                 hit.prim = -2;
@@ -1008,29 +1017,36 @@ HYB_HD void trace_ray(const TraceArgs& a, int64_t i, int* stack, int stride) {
             const float t2 = fmaxf(fmaf(-a.tau_end, a.h, tmax), t1);
             const bool sort = !(a.tau <= kShortSegment && a.tau_end <= kShortSegment);
             if (t2 > t1 || (a.tau == 0.0f && a.tau_end == 0.0f)) {
-                const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, t1, t2, cnt);
+                const float t = df_first_root<FMT, COUNT>(g, ox, oy, oz, dx, dy, dz, ray_inv(dx, dy, dz), t1, t2, cnt);
                 if (t != __builtin_inff()) {  // NaN: see df_first_root
                     hit.t = t;
                     hit.prim = -2;
                 }
             }
             if (hit.prim == -1 && t1 > tmin)
-                hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride, cnt,
+                hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, ray_inv(dx, dy, dz), tmin,
+                                                    t1, stack, stride, cnt,
                                                     entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1), sort);
             if (hit.prim == -1 && tmax > t2)
-                hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, t2, tmax, stack, stride, cnt,
+                hit = bvh_closest<COUNT, true, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, ray_inv(dx, dy, dz), t2,
+                                                    tmax, stack, stride, cnt,
                                                     entry_node(a, ox, oy, oz, dx, dy, dz, t2, tmax), sort);
         } else {
             // Eq. (2) with two sub-queries processed in order (first hit):
             // triangles on [tmin, t1]; the distance field on [t1, tmax] only
-            // when the first sub-query found nothing.
+            // when the first sub-query found nothing.  Both slab tests use
+            // the same 1 / d (the other modes form it where they use it: kept
+            // across the shadow query's march it cost that kernel a
+            // wavefront per SIMD).
+            const RayInv inv = ray_inv(dx, dy, dz);
             const float t1 = fminf(fmaf(a.tau, a.h, tmin), tmax);
             if (t1 > tmin)
-                hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, tmin, t1, stack, stride,
-                                                     cnt, entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1),
+                hit = bvh_closest<COUNT, false, LDS>(a.nodes, a.tris, ox, oy, oz, dx, dy, dz, inv, tmin, t1, stack,
+                                                     stride, cnt, entry_node(a, ox, oy, oz, dx, dy, dz, tmin, t1),
                                                      !(a.tau <= kShortSegment));
             if (hit.prim < 0 && (t1 < tmax || a.tau == 0.0f)) {
-                const float t = df_first_root<FMT, COUNT, FMT == kI8>(g, ox, oy, oz, dx, dy, dz, t1, tmax, cnt);
+                // I8 forms its solves again (df_resolve, REFORM): seven wavefronts per SIMD
+                const float t = df_first_root<FMT, COUNT, FMT == kI8>(g, ox, oy, oz, dx, dy, dz, inv, t1, tmax, cnt);
                 if (t != __builtin_inff()) {  // NaN: see df_first_root
                     hit.t = t;
                     hit.prim = -2;
