@@ -74,7 +74,7 @@ typedef struct hyb_sdf_s* hyb_sdf; /* distance-field grid; library-owned device 
  * 32 samples per 8 cells, for F32 and for F16 grids with n >= 205; one cell
  * with its 8 nodes for smaller F16 grids; for I8 one cell's 8 codes followed
  * by its block's scale, 12 bytes), so the device memory of a grid is n^3 FP32
- * values plus that copy.
+ * values plus that copy (and, for I8, its ceil((n - 1) / 8)^3 block scales).
  * Every interface that takes or returns grid values (hyb_sdf_from_grid,
  * hyb_sdf_read, hyb_df_backward) uses the linear n^3 order, x fastest. */
 typedef enum {
