@@ -30,7 +30,7 @@ constexpr int kWave = 64;
 // compiler takes 83 registers and runs five, 6% slower on the 64-scene batch.
 // The compact formats would spill at six and keep five.
 template <int FMT, int LDS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FMT == kF32 ? 6 : 5))) void k_trace_batch(
+__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(FMT == kF32 ? 6 : 5))) void k_trace_batch(
     BatchArgs b, const TraceArgs* __restrict__ scenes) {
     extern __shared__ int s_stack[];
     const int lane = threadIdx.x & (kWave - 1);
@@ -57,9 +57,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FMT == k
             // F16 scenes may differ in brick layout (a.fmt is the same for
             // the whole wavefront)
             if (FMT == kF16 && a.fmt == kF16B2)
-                trace_ray<kCombined, kF16B2, false, LDS>(a, i, s_stack + threadIdx.x, kBlock);
+                trace_ray<kCombined, kF16B2, false, LDS>(a, i, s_stack + threadIdx.x, kBatchBlock);
             else
-                trace_ray<kCombined, FMT, false, LDS>(a, i, s_stack + threadIdx.x, kBlock);
+                trace_ray<kCombined, FMT, false, LDS>(a, i, s_stack + threadIdx.x, kBatchBlock);
         }
     }
 }
@@ -68,15 +68,15 @@ __global__ void k_queue_reset(uint32_t* counter) {
     if (threadIdx.x == 0) counter[0] = 0u;
 }
 
-__global__ __launch_bounds__(kBlock) void k_count_mismatch(const float* __restrict__ t, const int32_t* __restrict__ prim,
+__global__ __launch_bounds__(kBatchBlock) void k_count_mismatch(const float* __restrict__ t, const int32_t* __restrict__ prim,
                                                           const float* __restrict__ t_ref,
                                                           const int32_t* __restrict__ prim_ref,
                                                           const float* __restrict__ dx, const float* __restrict__ dy,
                                                           const float* __restrict__ dz, int64_t n, float h,
                                                           unsigned long long* count) {
-    __shared__ unsigned int s_sum[kBlock / kWave];
+    __shared__ unsigned int s_sum[kBatchBlock / kWave];
     unsigned int c = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = (int64_t)blockIdx.x * kBatchBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBatchBlock) {
         const bool hit = prim[i] != -1, hit_ref = prim_ref[i] != -1;
         if (hit != hit_ref) {
             ++c;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_count_mismatch(const float* __restri
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long s = 0;
-        for (int k = 0; k < kBlock / kWave; ++k) s += s_sum[k];
+        for (int k = 0; k < kBatchBlock / kWave; ++k) s += s_sum[k];
         if (s) atomicAdd(count, s);
     }
 }
@@ -180,7 +180,7 @@ const void* batch_kernel(int fmt, int lds_depth) {
     return nullptr;
 }
 
-size_t batch_lds_bytes(int lds_depth) { return sizeof(int) * (size_t)lds_depth * kBlock; }
+size_t batch_lds_bytes(int lds_depth) { return sizeof(int) * (size_t)lds_depth * kBatchBlock; }
 
 const void* queue_reset_kernel() { return reinterpret_cast<const void*>(&k_queue_reset); }
 
@@ -188,8 +188,8 @@ hipError_t launch_count_mismatch(const float* t, const int32_t* prim, const floa
                                  const float* dx, const float* dy, const float* dz, int64_t n, float h,
                                  unsigned long long* count, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 4096);
-    hipLaunchKernelGGL(k_count_mismatch, dim3((unsigned)blocks), dim3(kBlock), 0, stream, t, prim, t_ref, prim_ref, dx,
+    const int64_t blocks = std::min<int64_t>((n + kBatchBlock - 1) / kBatchBlock, 4096);
+    hipLaunchKernelGGL(k_count_mismatch, dim3((unsigned)blocks), dim3(kBatchBlock), 0, stream, t, prim, t_ref, prim_ref, dx,
                        dy, dz, n, h, count);
     return hipGetLastError();
 }
@@ -276,7 +276,7 @@ hyb_status persistent_grid(int fmt, const hyb_batch_config& cfg, int n_cu, uint6
     const void* fn = hyb::batch_kernel(fmt, cfg.lds_depth);
     if (!fn) return HYB_ERR_UNSUPPORTED;
     int occ = 0;
-    HYB_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, hyb::kBlock, hyb::batch_lds_bytes(cfg.lds_depth)));
+    HYB_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, hyb::kBatchBlock, hyb::batch_lds_bytes(cfg.lds_depth)));
     const int64_t per_cu = std::max(1, std::min(occ, cfg.blocks_per_cu));
     const int64_t waves_needed = (static_cast<int64_t>(work_items) + 3) / 4;  // 4 wavefronts per block
     *grid = dim3(static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(per_cu * n_cu, waves_needed))));
@@ -349,7 +349,7 @@ hipError_t launch_eager(hyb_batch_s* b, hipStream_t stream) {
     if (e != hipSuccess || b->kargs.n_items == 0) return e;
     const hyb::TraceArgs* scenes = b->d_args;
     void* trace_args[] = {&b->kargs, &scenes};
-    return hipLaunchKernel(hyb::batch_kernel(b->fmt, b->cfg.lds_depth), b->grid, dim3(hyb::kBlock), trace_args,
+    return hipLaunchKernel(hyb::batch_kernel(b->fmt, b->cfg.lds_depth), b->grid, dim3(hyb::kBatchBlock), trace_args,
                            hyb::batch_lds_bytes(b->cfg.lds_depth), stream);
 }
 
@@ -374,7 +374,7 @@ hipError_t build_graph(hyb_batch_s* b) {
         std::memset(&p1, 0, sizeof(p1));
         p1.func = const_cast<void*>(hyb::batch_kernel(b->fmt, b->cfg.lds_depth));
         p1.gridDim = b->grid;
-        p1.blockDim = dim3(hyb::kBlock);
+        p1.blockDim = dim3(hyb::kBatchBlock);
         p1.sharedMemBytes = static_cast<unsigned>(hyb::batch_lds_bytes(b->cfg.lds_depth));
         p1.kernelParams = trace_args;
         e = hipGraphAddKernelNode(&trace_node, b->graph, &reset_node, 1, &p1);
@@ -672,7 +672,7 @@ hyb_status hyb_batch_launch_static(const hyb_batch_item* items, int32_t n_items,
     kargs.n_items = static_cast<uint32_t>(total);
     kargs.rays_per_item = cfg.rays_per_item;
     void* trace_args[] = {&kargs, &scenes};
-    return from_hip(hipLaunchKernel(hyb::batch_kernel(fmt, cfg.lds_depth), grid, dim3(hyb::kBlock), trace_args,
+    return from_hip(hipLaunchKernel(hyb::batch_kernel(fmt, cfg.lds_depth), grid, dim3(hyb::kBatchBlock), trace_args,
                                     hyb::batch_lds_bytes(cfg.lds_depth), st));
 }
 

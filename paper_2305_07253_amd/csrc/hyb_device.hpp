@@ -19,7 +19,13 @@
 
 namespace hyb {
 
-constexpr int kBlock = 256;      // threads per block: 4 wavefronts
+// Threads per block of the trace kernels: one wavefront.  A block keeps its
+// slot and LDS until its last wavefront ends, and the march's wavefronts end
+// at very different times, so with one wavefront per block none waits on
+// another's long rays (measured against 4 and 2 wavefronts per block: 1-5%
+// faster on every timed query, the same hits).
+constexpr int kBlock = 64;
+constexpr int kBatchBlock = 256;  // the persistent batch kernel's blocks: 4 wavefronts
 constexpr int kXcds = 8;         // MI355X: 8 accelerator dies of 32 CUs, one L2 each
 constexpr int kLdsDepth = 16;    // stack entries per lane held in LDS
 constexpr int kStackDepth = 96;  // total stack entries per lane (LDS + spill); the BVH builder bounds the need
@@ -56,11 +62,11 @@ HYB_HD uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t run) {
     return (k / run * kXcds + b % kXcds) * run + k % run;
 }
 
-// Run length of the trace kernels: 16 blocks (4,096 rays) per die at a time
-// (on the GI rays 3% faster than plain order at threshold 0, and than 4 or
-// 64; one contiguous eighth per die made the triangle-only query 4% slower,
-// the dies finishing unevenly).
-constexpr uint32_t kXcdRun = 16;
+// Run length of the trace kernels: 64 blocks (4,096 rays) per die at a time
+// (on the GI rays 3% faster than plain order at threshold 0, and than runs
+// of 1,024 or 16,384 rays; one contiguous eighth per die made the
+// triangle-only query 4% slower, the dies finishing unevenly).
+constexpr uint32_t kXcdRun = 64;
 
 // ---------------------------------------------------------------------------
 // triangle test
