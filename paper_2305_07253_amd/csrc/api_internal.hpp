@@ -174,7 +174,14 @@ inline void fill_trace_args(hyb::TraceArgs& a, const hyb_rays* rays, hyb_hits* h
     a.n = n;
 }
 
+// Bytes of the kernels' bricked copy of a grid.
+inline int64_t copy_bytes(const hyb_sdf_s* s) {
+    const int64_t elem = s->layout == hyb::kF32 ? 4 : (s->layout == hyb::kI8 ? 1 : 2);
+    return hyb::brick_storage(s->layout, s->n) * elem;
+}
+
 inline void fill_scene(hyb::TraceArgs& a, const hyb_bvh_s* b, const hyb_sdf_s* s) {
+    a.xcd_run = hyb::xcd_run_for(s ? copy_bytes(s) : 0);
     if (b) {
         a.nodes = b->nodes4;
         a.entry = b->entry_res ? b->entry : nullptr;

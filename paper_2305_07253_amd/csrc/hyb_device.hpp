@@ -62,11 +62,20 @@ HYB_HD uint32_t xcd_block(uint32_t b, uint32_t nb, uint32_t run) {
     return (k / run * kXcds + b % kXcds) * run + k % run;
 }
 
-// Run length of the trace kernels: 64 blocks (4,096 rays) per die at a time
-// (on the GI rays 3% faster than plain order at threshold 0, and than runs
-// of 1,024 or 16,384 rays; one contiguous eighth per die made the
-// triangle-only query 4% slower, the dies finishing unevenly).
+// Run length of the trace kernels: consecutive blocks (one wavefront each)
+// a die takes at a time.  64 blocks (4,096 rays) on the GI rays: 3% faster
+// than plain order at threshold 0, and faster than runs of 1,024 to 32,768
+// rays (one contiguous eighth per die made the triangle-only query 4% slower,
+// the dies finishing unevenly).  Grids whose kernel copy passes 128 MiB, half
+// the MALL, take runs of 8,192 rays: on the 256^3 grid F32 3% and I8 6%
+// faster at threshold 0 (F16 in its 128 MiB two-cell copy the same either
+// way).
 constexpr uint32_t kXcdRun = 64;
+constexpr uint32_t kXcdRunLargeGrid = 128;
+
+inline uint32_t xcd_run_for(int64_t copy_bytes) {
+    return copy_bytes > (int64_t(128) << 20) ? kXcdRunLargeGrid : kXcdRun;
+}
 
 // ---------------------------------------------------------------------------
 // triangle test

@@ -30,6 +30,7 @@ struct TraceArgs {
     float slope_x, slope_y, slope_z;  // per-axis bounds of the interpolant's partial derivatives
     // query
     float tmax, tau, tau_end;
+    uint32_t xcd_run;  // blocks per die run of the trace kernels (xcd_block)
     int64_t n;
     double inv_hd;  // 1 / h in FP64 (scales the distance field's FP64 ray position)
     // Step bounds on the device (null: the fields above hold them): the grid

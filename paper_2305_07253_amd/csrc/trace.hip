@@ -25,7 +25,7 @@ template <int MODE, int FMT, bool COUNT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(trace_waves<MODE, FMT, COUNT>())))
 void k_trace(TraceArgs a) {
     extern __shared__ int s_stack[];
-    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x, kXcdRun) * kBlock + threadIdx.x;
+    const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x, a.xcd_run) * kBlock + threadIdx.x;
     if (i >= a.n) return;
     trace_ray<MODE, FMT, COUNT>(a, i, s_stack + threadIdx.x, kBlock);
 }
@@ -50,8 +50,10 @@ static hipError_t launch_fmt(const TraceArgs& a, hipStream_t stream) {
     }
 }
 
-hipError_t launch_trace(int mode, bool counters, const TraceArgs& a, hipStream_t stream) {
-    if (a.n <= 0) return hipSuccess;
+hipError_t launch_trace(int mode, bool counters, const TraceArgs& args, hipStream_t stream) {
+    if (args.n <= 0) return hipSuccess;
+    TraceArgs a = args;
+    if (a.xcd_run == 0) a.xcd_run = kXcdRun;  // xcd_block needs a run of at least 1
     switch (mode * 2 + (counters ? 1 : 0)) {
         case 0: return launch_fmt<kCombined, false>(a, stream);
         case 1: return launch_fmt<kCombined, true>(a, stream);
