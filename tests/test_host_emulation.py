@@ -207,7 +207,7 @@ def test_grid_sizes_with_partial_bricks(emu, orc, tiny, n):
             parity.check(got, ref, m, c, label="emu n=%d fmt %d tau %s" % (n, fmt, tau))
 
 
-@pytest.mark.parametrize("run", [1, 16, 100])
+@pytest.mark.parametrize("run", [1, 16, 64, 100, 128])
 def test_block_order_is_a_permutation(emu, run):
     """The trace kernels' workgroup-to-block map: every block of a launch is
     processed exactly once, and within each full group of 8 * run blocks the
