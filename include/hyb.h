@@ -295,10 +295,17 @@ hyb_status hyb_trace_counters(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, in
  *   t_hit          device, n floats: the forward result
  *   grad_t         device, n floats: d loss / d t_hit
  *   grad_grid      device, n_grid^3 floats (x fastest): accumulated into (+=)
- * The sdf must be FP32 (HYB_SDF_F32).  Accumulation uses float atomics: sums
- * agree across runs up to FP32 rounding of the order of additions.
+ * The sdf must be FP32 (HYB_SDF_F32).  The rays are sorted by hit cell and
+ * each wavefront sums the rays of one cell before adding with float atomics:
+ * sums agree across runs up to FP32 rounding of the order of additions.  The
+ * sort's buffers (16 n bytes plus the sort's scratch) live in the sdf handle
+ * until hyb_sdf_destroy: a call with more rays than any before it on the
+ * handle allocates them (device memory, after waiting for the device to free
+ * the smaller ones), later calls allocate nothing.  Calls on one handle that
+ * overlap on different streams share the buffers and race.
  * Errors: HYB_ERR_INVALID_ARG for NULL pointers, n < 0 or n > HYB_MAX_RAYS,
- * NaN/negative tmax; HYB_ERR_UNSUPPORTED for a compact-format sdf. */
+ * NaN/negative tmax; HYB_ERR_UNSUPPORTED for a compact-format sdf;
+ * HYB_ERR_OOM when the buffers cannot be allocated. */
 hyb_status hyb_df_backward(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, const float* t_hit,
                            const float* grad_t, float* grad_grid, void* stream);
 

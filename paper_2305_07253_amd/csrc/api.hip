@@ -238,6 +238,7 @@ hyb_status hyb_sdf_destroy(hyb_sdf sdf) {
     if (sdf->scales) (void)hipFree(sdf->scales);
     if (sdf->blocks) (void)hipFree(sdf->blocks);
     if (sdf->dev_bounds) (void)hipFree(sdf->dev_bounds);
+    if (sdf->bwd_ws) (void)hipFree(sdf->bwd_ws);
     delete sdf;
     return HYB_OK;
 }
@@ -305,7 +306,17 @@ hyb_status hyb_df_backward(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float t
     hyb_hits none = {nullptr, nullptr, nullptr, nullptr};
     fill_trace_args(a, rays, &none, n, tmax, 0.0f);
     fill_scene(a, nullptr, sdf);
-    return from_hip(hyb::launch_df_backward(a, t_hit, grad_t, grad_grid, static_cast<hipStream_t>(stream)));
+    const size_t need = hyb::df_backward_workspace(n, sdf->n);
+    if (need == 0) return HYB_ERR_HIP;
+    if (sdf->bwd_ws_bytes < need) {
+        if (sdf->bwd_ws) (void)hipFree(sdf->bwd_ws);
+        sdf->bwd_ws = nullptr;
+        sdf->bwd_ws_bytes = 0;
+        HYB_TRY(hipMalloc(&sdf->bwd_ws, need));
+        sdf->bwd_ws_bytes = need;
+    }
+    return from_hip(hyb::launch_df_backward(a, t_hit, grad_t, grad_grid, sdf->bwd_ws, sdf->bwd_ws_bytes,
+                                            static_cast<hipStream_t>(stream)));
 }
 
 hyb_status hyb_trace_counters(hyb_bvh bvh, hyb_sdf sdf, const hyb_rays* rays, int64_t n, float tmax, float threshold,

@@ -42,6 +42,8 @@ struct hyb_sdf_s {
     uint64_t version = 0;     // bumped whenever the samples and bounds change (batches re-read them)
     float* dev_bounds = nullptr;  // hyb::kDeviceBounds floats: the bounds of a deferred update
     bool deferred = false;        // the last update was deferred: the kernels read dev_bounds
+    void* bwd_ws = nullptr;       // hyb_df_backward's sort buffers, grown on demand
+    size_t bwd_ws_bytes = 0;
 };
 
 namespace hyb_api {

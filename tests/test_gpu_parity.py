@@ -447,6 +447,37 @@ def test_df_backward_vs_oracle_gradient(hyb, orc, tiny, tiny_dev):
     assert torch.allclose(grad, grad2, rtol=1e-5, atol=1e-6 * scale)
 
 
+def test_df_backward_long_runs_of_one_cell(hyb, orc, tiny, tiny_dev):
+    """The backward sorts the rays by hit cell and sums each run of one cell
+    inside a wavefront before adding: 40 well-posed rays repeated 1 to 150
+    times (runs across several wavefronts), shuffled, 1,000 rays in all (a
+    ragged last wavefront), each with its own grad_t, against the oracle's
+    FP64 derivatives summed per copy."""
+    import torch
+    grid, g4 = tiny["grid"], tiny["grid4"]
+    sel, t_ref = _well_posed(orc, tiny)
+    base = np.nonzero(sel)[0][:40]
+    rng = np.random.default_rng(11)
+    reps = rng.integers(1, 60, size=len(base))
+    reps[:3] = [150, 97, 64]
+    idx = np.repeat(base, reps)
+    idx = idx[rng.permutation(len(idx))][:1000]
+    assert len(idx) == 1000
+    gt = rng.standard_normal(len(idx)).astype(np.float32)
+    R = to_dev(tiny["free"].subset(idx).soa())
+    t, _, _, _ = hyb.trace_df(tiny_dev["sdf"], R, 2.0)
+    grad = torch.zeros(32 ** 3, dtype=torch.float32, device="cuda")
+    hyb.df_backward(tiny_dev["sdf"], R, 2.0, t, to_dev(gt), grad)
+    got = grad.cpu().numpy().astype(np.float64)
+    nodes, dt = orc.df_grad(grid, g4, tiny["free"].soa(), t_ref, 0.0, 2.0)
+    ref = np.zeros(32 ** 3)
+    keep = nodes[idx] >= 0
+    np.add.at(ref, nodes[idx][keep], (gt.astype(np.float64)[:, None] * dt[idx])[keep])
+    scale = np.abs(ref).max()
+    assert scale > 0.5 and (ref != 0).sum() >= 8 * 30
+    assert np.abs(got - ref).max() <= 1e-4 * scale, np.abs(got - ref).max()
+
+
 def test_df_backward_finite_differences(hyb, orc, tiny):
     """Central differences through the GPU forward on 64 voxels with non-zero
     gradient (rays clear of cell faces and well conditioned)."""
