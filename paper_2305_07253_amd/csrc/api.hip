@@ -306,7 +306,11 @@ hyb_status hyb_df_backward(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float t
     hyb_hits none = {nullptr, nullptr, nullptr, nullptr};
     fill_trace_args(a, rays, &none, n, tmax, 0.0f);
     fill_scene(a, nullptr, sdf);
-    const size_t need = hyb::df_backward_workspace(n, sdf->n);
+    if (n != sdf->bwd_n) {  // sizing the sort costs host time: once per ray count
+        sdf->bwd_need = hyb::df_backward_workspace(n, sdf->n);
+        sdf->bwd_n = n;
+    }
+    const size_t need = sdf->bwd_need;
     if (need == 0) return HYB_ERR_HIP;
     if (sdf->bwd_ws_bytes < need) {
         if (sdf->bwd_ws) (void)hipFree(sdf->bwd_ws);
@@ -315,7 +319,7 @@ hyb_status hyb_df_backward(hyb_sdf sdf, const hyb_rays* rays, int64_t n, float t
         HYB_TRY(hipMalloc(&sdf->bwd_ws, need));
         sdf->bwd_ws_bytes = need;
     }
-    return from_hip(hyb::launch_df_backward(a, t_hit, grad_t, grad_grid, sdf->bwd_ws, sdf->bwd_ws_bytes,
+    return from_hip(hyb::launch_df_backward(a, t_hit, grad_t, grad_grid, sdf->bwd_ws, need,
                                             static_cast<hipStream_t>(stream)));
 }
 

@@ -44,6 +44,8 @@ struct hyb_sdf_s {
     bool deferred = false;        // the last update was deferred: the kernels read dev_bounds
     void* bwd_ws = nullptr;       // hyb_df_backward's sort buffers, grown on demand
     size_t bwd_ws_bytes = 0;
+    int64_t bwd_n = 0;            // the ray count whose buffer size bwd_need holds
+    size_t bwd_need = 0;
 };
 
 namespace hyb_api {

@@ -9,7 +9,7 @@
 // wavefront sums the contributions of consecutive equal keys before the last
 // lane of each run adds them: 8 adds per (wavefront, cell) instead of per
 // ray.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "hyb_device.hpp"
 #include "kernels.hpp"
@@ -18,6 +18,13 @@ namespace hyb {
 namespace {
 
 constexpr int kBwdBlock = 256;
+
+// The (cell, ray) pairs are sorted by rocPRIM's onesweep radix sort from 64k
+// pairs up: its default switches to a block sort plus merge passes up to 1M
+// pairs, which took 154 us of a 241 us backward on 1M rays (ten merge
+// passes) where onesweep takes three passes over 22-bit keys.
+using BwdSortConfig =
+    rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config, rocprim::default_config, 65536>;
 
 // Contributions of ray i (grad_t times d t / d sample of its cell's 8
 // corners, corner order of `corners`) and the linear index of the cell's
@@ -106,10 +113,9 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t sort_temp_bytes(int64_t n, int32_t n_grid) {
     size_t bytes = 0;
-    const hipError_t e = hipcub::DeviceRadixSort::SortPairs(
-        nullptr, bytes, static_cast<const uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr),
-        static_cast<const uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr), static_cast<int>(n), 0,
-        key_bits(n_grid), hipStream_t(nullptr));
+    rocprim::double_buffer<uint32_t> keys(nullptr, nullptr), rays(nullptr, nullptr);
+    const hipError_t e = rocprim::radix_sort_pairs<BwdSortConfig>(nullptr, bytes, keys, rays, static_cast<int>(n), 0,
+                                                                  key_bits(n_grid), hipStream_t(nullptr));
     return e == hipSuccess ? bytes : 0;
 }
 
@@ -125,26 +131,27 @@ size_t df_backward_workspace(int64_t n, int32_t n_grid) {
 hipError_t launch_df_backward(const TraceArgs& a, const float* t_hit, const float* grad_t, float* grad_grid,
                               void* workspace, size_t workspace_bytes, hipStream_t stream) {
     if (a.n <= 0) return hipSuccess;
-    const size_t need = df_backward_workspace(a.n, a.n_grid);
-    if (need == 0 || !workspace || workspace_bytes < need) return hipErrorInvalidValue;
+    // four arrays of n words (keys and ray indices, each twice for the sort's
+    // passes), then the sort's scratch: the caller sized it with
+    // df_backward_workspace(a.n, a.n_grid)
     const size_t arr = align256(sizeof(uint32_t) * (size_t)a.n);
+    if (!workspace || workspace_bytes <= 4 * arr) return hipErrorInvalidValue;
     char* p = static_cast<char*>(workspace);
-    uint32_t* keys_in = reinterpret_cast<uint32_t*>(p);
-    uint32_t* keys_out = reinterpret_cast<uint32_t*>(p + arr);
-    uint32_t* rays_in = reinterpret_cast<uint32_t*>(p + 2 * arr);
-    uint32_t* rays_out = reinterpret_cast<uint32_t*>(p + 3 * arr);
-    void* temp = p + 4 * arr;
-    size_t temp_bytes = need - 4 * arr;
+    rocprim::double_buffer<uint32_t> keys(reinterpret_cast<uint32_t*>(p), reinterpret_cast<uint32_t*>(p + arr));
+    rocprim::double_buffer<uint32_t> rays(reinterpret_cast<uint32_t*>(p + 2 * arr),
+                                          reinterpret_cast<uint32_t*>(p + 3 * arr));
+    size_t temp_bytes = workspace_bytes - 4 * arr;
     const uint32_t none = key_none(a.n_grid);
     const unsigned blocks = (unsigned)((a.n + kBwdBlock - 1) / kBwdBlock);
-    hipLaunchKernelGGL(k_bwd_keys, dim3(blocks), dim3(kBwdBlock), 0, stream, a, t_hit, grad_t, keys_in, rays_in, none);
+    hipLaunchKernelGGL(k_bwd_keys, dim3(blocks), dim3(kBwdBlock), 0, stream, a, t_hit, grad_t, keys.current(),
+                       rays.current(), none);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, rays_in, rays_out,
-                                           static_cast<int>(a.n), 0, key_bits(a.n_grid), stream);
+    e = rocprim::radix_sort_pairs<BwdSortConfig>(p + 4 * arr, temp_bytes, keys, rays, static_cast<int>(a.n), 0,
+                                                 key_bits(a.n_grid), stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bwd_runs, dim3(blocks), dim3(kBwdBlock), 0, stream, a, t_hit, grad_t, keys_out, rays_out,
-                       grad_grid, none);
+    hipLaunchKernelGGL(k_bwd_runs, dim3(blocks), dim3(kBwdBlock), 0, stream, a, t_hit, grad_t, keys.current(),
+                       rays.current(), grad_grid, none);
     return hipGetLastError();
 }
 

@@ -85,8 +85,8 @@ hipError_t launch_quantize(int fmt, float* values, int32_t n, void* out, float* 
 
 // Scatter of d loss / d grid sample for distance-field hits (hyb_df_backward):
 // the rays are sorted by hit cell in `workspace` (device memory of at least
-// df_backward_workspace(a.n, a.n_grid) bytes, 0 when the sort cannot be
-// sized), and each wavefront adds once per cell.
+// df_backward_workspace(a.n, a.n_grid) bytes, which is 0 when the sort cannot
+// be sized), and each wavefront adds once per cell.
 size_t df_backward_workspace(int64_t n, int32_t n_grid);
 hipError_t launch_df_backward(const TraceArgs& a, const float* t_hit, const float* grad_t, float* grad_grid,
                               void* workspace, size_t workspace_bytes, hipStream_t stream);
