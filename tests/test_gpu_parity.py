@@ -478,6 +478,41 @@ def test_df_backward_long_runs_of_one_cell(hyb, orc, tiny, tiny_dev):
     assert np.abs(got - ref).max() <= 1e-4 * scale, np.abs(got - ref).max()
 
 
+@pytest.mark.parametrize("n", [1, 63, 65, 257])
+def test_df_backward_small_and_degenerate(hyb, orc, tiny, tiny_dev, n):
+    """Ragged ray counts below one wavefront up to a few (the sort's
+    single-block path), against the oracle; then rays that add nothing (all
+    grad_t zero, or every ray a miss) leave the gradient untouched, and a
+    second call with more rays than the first grows the handle's buffers."""
+    import torch
+    grid, g4 = tiny["grid"], tiny["grid4"]
+    sel, t_ref = _well_posed(orc, tiny)
+    idx = np.nonzero(sel)[0][:n]
+    R = to_dev(tiny["free"].subset(idx).soa())
+    sdf = hyb.sdf_from_grid(torch.from_numpy(grid.reshape(-1).copy()).cuda(), g4)
+    t, _, _, _ = hyb.trace_df(sdf, R, 2.0)
+    grad = torch.zeros(32 ** 3, dtype=torch.float32, device="cuda")
+    hyb.df_backward(sdf, R, 2.0, t, torch.ones_like(t), grad)
+    nodes, dt = orc.df_grad(grid, g4, tiny["free"].soa(), t_ref, 0.0, 2.0)
+    ref = np.zeros(32 ** 3)
+    keep = nodes[idx] >= 0
+    np.add.at(ref, nodes[idx][keep], dt[idx][keep])
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.abs(grad.cpu().numpy().astype(np.float64) - ref).max() <= 1e-4 * scale
+    before = grad.clone()
+    hyb.df_backward(sdf, R, 2.0, t, torch.zeros_like(t), grad)
+    miss = torch.full_like(t, float("inf"))
+    hyb.df_backward(sdf, R, 2.0, miss, torch.ones_like(t), grad)
+    assert torch.equal(grad, before)
+    # more rays than any call before on this handle: the buffers grow
+    R2 = to_dev(tiny["free"].subset(np.nonzero(sel)[0][:4 * n + 64]).soa())
+    t2, _, _, _ = hyb.trace_df(sdf, R2, 2.0)
+    g2 = torch.zeros_like(grad)
+    hyb.df_backward(sdf, R2, 2.0, t2, torch.ones_like(t2), g2)
+    assert torch.count_nonzero(g2) >= torch.count_nonzero(grad)
+
+
 def test_df_backward_finite_differences(hyb, orc, tiny):
     """Central differences through the GPU forward on 64 voxels with non-zero
     gradient (rays clear of cell faces and well conditioned)."""
