@@ -62,13 +62,37 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def time_launches(fn, stream, reps, warmup):
-    """Average duration of fn() (one kernel launch) over `reps` launches,
-    bracketed by HIP events on the stream the kernel runs on."""
+# Untimed load before every timed section: after the host work between
+# sections (a fraction of a second with the GPU idle) the first launches run
+# up to 10% slower until the GPU's clock has settled under load, which takes
+# some tens of ms (0.33 ms per launch of the threshold-0 query after 3 warm
+# launches, 0.300 ms after 30 ms or more of them).
+SETTLE_MS = 50.0
+
+
+def settle(fn, warmup):
+    """`warmup` untimed calls of fn(), then about SETTLE_MS more of them,
+    issued back to back with one wait at the end (frequent waits between
+    launches left the following launches slower for a few ms)."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    one = max(time.perf_counter() - t0, 1e-5)
+    for _ in range(min(int(SETTLE_MS * 1e-3 / one), 5000)):
+        fn()
+    torch.cuda.synchronize()
+
+
+def time_launches(fn, stream, reps, warmup):
+    """Average duration of fn() (one kernel launch) over `reps` launches,
+    bracketed by HIP events on the stream the kernel runs on, after `warmup`
+    untimed launches and SETTLE_MS of untimed load."""
+    import torch
+    settle(fn, warmup)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record(stream)
     for _ in range(reps):
@@ -167,7 +191,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed launches before the timed region (200 at threshold 0 are about 60 ms of load, "
+                         "enough for the GPU's clock to settle)")
     ap.add_argument("--reps", type=int, default=10, help="launches per sweep point")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="rays for the CPU oracle baseline (0: skip)")
     ap.add_argument("--tau", type=float, default=None,
@@ -295,19 +321,11 @@ def main():
 
     c, work = counts(tau)
 
-    # timed region: K steps of the combined query at the chosen threshold
+    # timed region: K steps of the combined query at the chosen threshold,
+    # right after the warm-up
     for _ in range(args.warmup):
         hyb.trace(bvh, sdf128, R, TMAX, tau, out=out)
     torch.cuda.synchronize()
-    # the median of K single launches, each bracketed by its own events (run
-    # before the timed region, whose launches stay the last K of the kernel)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    for e0, e1 in evs:
-        e0.record(stream)
-        hyb.trace(bvh, sdf128, R, TMAX, tau, out=out)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    ms_median = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     wall0 = time.time()
     start.record(stream)
@@ -318,6 +336,17 @@ def main():
     wall = time.time() - wall0
     ms_step = start.elapsed_time(stop) / args.steps
     value = n / ms_step / 1e3  # Mrays/s
+    # the median of K single launches, each bracketed by its own events, after
+    # the timed region (run between the warm-up and the timed region, these
+    # event-bracketed launches left the next few ms of back-to-back launches
+    # up to 10% slower); the timed launches are the K before the last K
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        hyb.trace(bvh, sdf128, R, TMAX, tau, out=out)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms_median = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
 
     # the combined query that runs both techniques on every ray (threshold 1
     # voxel): its own time, work, roofline and error
@@ -435,6 +464,11 @@ def run_extras(args, torch, hyb, W, dev, stream, scene, gb, bvh, g128):
         ((d * d).sum() / use.sum().clamp(min=1)).backward()
         opt.step()
 
+    # the GPU settles on the forward query, which leaves the grid alone; the
+    # optimiser then takes a fixed number of steps, so the timed steps and
+    # kernels always see the same grid
+    o2 = hyb.alloc_hits(rr.n)
+    settle(lambda: hyb.trace_df(handle, RR, TMAX, out=o2), 0)
     for _ in range(5):
         adam_step()
     torch.cuda.synchronize()
@@ -443,7 +477,6 @@ def run_extras(args, torch, hyb, W, dev, stream, scene, gb, bvh, g128):
         adam_step()
     torch.cuda.synchronize()
     step_ms = (time.time() - t1) * 1e3 / 20
-    o2 = hyb.alloc_hits(rr.n)
     ms_fwd = time_launches(lambda: hyb.trace_df(handle, RR, TMAX, out=o2), stream, args.reps, 2)
     grad = torch.zeros(128 ** 3, device=dev)
     ones = torch.ones(rr.n, device=dev)

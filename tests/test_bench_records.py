@@ -27,8 +27,11 @@ def test_counter_record_matches_the_kernel_sources(bench):
         # (about 650 B/ray at threshold 0, 1.4 kB at 1, for 2,073,600 rays)
         traffic = rec["read_bytes"] + rec["write_bytes"]
         assert 0.5e9 < traffic < 4e9
+        # VALU issue at 4 cycles per wave64 instruction and 2.4 GHz: the kernel
+        # is issue-bound, so this is most of the dispatch; the estimate may pass
+        # it by a few percent (7% at threshold 1 with the clock settled)
         issue_us = rec["valu_insts"] * 4.0 / bench.N_SIMD / bench.CLOCK_HZ * 1e6
-        assert 0.5 * rec["kernel_us"] < issue_us <= 1.05 * rec["kernel_us"]
+        assert 0.5 * rec["kernel_us"] < issue_us <= 1.15 * rec["kernel_us"]
         assert 0.0 < rec["lane_utilisation"] <= 1.0 and 0.0 < rec["l2_hit"] <= 1.0
 
 
