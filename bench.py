@@ -263,6 +263,10 @@ def main():
     o_np, d_np = rays.o.astype(np.float64), rays.d.astype(np.float64)
 
     if args.profile:
+        # counters do not depend on the clock: each phase runs its warm-up and
+        # steps only, so a counter run has the same dispatches every time
+        global SETTLE_MS
+        SETTLE_MS = 0.0
         tau = 0.0 if args.tau is None else args.tau
         a = torch.empty(64 << 20, dtype=torch.float32, device=dev)  # 256 MiB copy probe
         b = torch.empty_like(a)
